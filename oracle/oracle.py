@@ -1,0 +1,200 @@
+"""ctypes front end of the FP64 CPU oracle (``liblbe_oracle.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product package.  The
+oracle shares no code with the HIP library; this wrapper marshals arguments
+and nothing else (all arithmetic lives in ``lbe_oracle.c``).
+
+Parameters are the same plain dict the workload generator returns (keys
+``nx ny walls_y rho cv tau_f tau_T tau_g mobility width beta sigma0 sigmaT
+Tref force p0``); the oracle derives eps, alpha, kcap and Gamma itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbe_oracle.so")
+SRC_PATH = os.path.join(_HERE, "lbe_oracle.c")
+
+N_DIAG = 7
+DIAG_KEYS = ("mass", "energy", "sum_cy", "sum_cx", "mass_thr", "sum_cuy_thr",
+             "n_nonfinite")
+INTERMEDIATE_KEYS = ("c", "T", "p", "jx", "jy", "gcx", "gcy", "lapc", "gTx",
+                     "gTy", "gpx", "gpy", "mu", "Fx", "Fy", "ux", "uy")
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("NX", ctypes.c_int32), ("NY", ctypes.c_int32),
+        ("x0", ctypes.c_int32), ("y0", ctypes.c_int32),
+        ("wx", ctypes.c_int32), ("wy", ctypes.c_int32),
+        ("walls_y", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("rho", ctypes.c_double), ("cv", ctypes.c_double),
+        ("tau_f", ctypes.c_double * 2), ("tau_T", ctypes.c_double * 2),
+        ("tau_g", ctypes.c_double), ("mobility", ctypes.c_double),
+        ("width", ctypes.c_double), ("beta", ctypes.c_double),
+        ("sigma0", ctypes.c_double), ("sigmaT", ctypes.c_double),
+        ("Tref", ctypes.c_double), ("force", ctypes.c_double * 2),
+        ("p0", ctypes.c_double),
+    ]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (-O2 -ffp-contract=off, OpenMP)."""
+    import subprocess
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-Wextra", "-o", LIB_PATH, SRC_PATH, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH) or (
+                os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH)):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [ctypes.POINTER(_Params), dp, dp]
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_init.argtypes = [ctypes.c_void_p, dp, dp]
+        L.orc_set_state.argtypes = [ctypes.c_void_p, dp]
+        L.orc_get_state.argtypes = [ctypes.c_void_p, dp]
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_fields.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp]
+        L.orc_intermediates.argtypes = [ctypes.c_void_p, dp]
+        L.orc_diag.argtypes = [ctypes.c_void_p, dp]
+        L.orc_collide_site.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp]
+        L.orc_derived.argtypes = [ctypes.POINTER(_Params), dp]
+        L.orc_sizeof_params.restype = ctypes.c_int
+        assert L.orc_sizeof_params() == ctypes.sizeof(_Params)
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _make_params(p: dict, window=None) -> _Params:
+    nx, ny = int(p["nx"]), int(p["ny"])
+    x0, y0, wx, wy = window if window is not None else (0, 0, nx, ny)
+    P = _Params()
+    P.NX, P.NY, P.x0, P.y0, P.wx, P.wy = nx, ny, x0, y0, wx, wy
+    P.walls_y = int(p.get("walls_y", 1))
+    P.rho, P.cv = float(p["rho"]), float(p["cv"])
+    P.tau_f[0], P.tau_f[1] = map(float, p["tau_f"])
+    P.tau_T[0], P.tau_T[1] = map(float, p["tau_T"])
+    P.tau_g, P.mobility = float(p["tau_g"]), float(p["mobility"])
+    P.width, P.beta = float(p["width"]), float(p["beta"])
+    P.sigma0, P.sigmaT, P.Tref = (float(p["sigma0"]), float(p["sigmaT"]),
+                                  float(p["Tref"]))
+    P.force[0], P.force[1] = map(float, p["force"])
+    P.p0 = float(p["p0"])
+    return P
+
+
+def derived(p: dict) -> dict:
+    out = np.zeros(4)
+    lib().orc_derived(ctypes.byref(_make_params(p)), _ptr(out))
+    return dict(eps=out[0], alpha=out[1], kcap=out[2], Gamma=out[3])
+
+
+def collide_site(p: dict, pre27, stencil7):
+    """Single-site collision: returns (post[27], aux dict)."""
+    pre = np.ascontiguousarray(pre27, dtype=np.float64)
+    st = np.ascontiguousarray(stencil7, dtype=np.float64)
+    out = np.zeros(27)
+    aux = np.zeros(11)
+    lib().orc_collide_site(ctypes.byref(_make_params(p)), _ptr(pre), _ptr(st),
+                           _ptr(out), _ptr(aux))
+    keys = ("c", "T", "p", "mu", "Fx", "Fy", "ux", "uy", "wf", "wT", "wg")
+    return out, dict(zip(keys, aux))
+
+
+class Oracle:
+    """A grid (or a window of one) advanced by the plain FP64 oracle.
+
+    ``window=(x0, y0, wx, wy)`` holds only that part of the global domain;
+    values whose dependence leaves the window come out as NaN.  Field arrays
+    are (wy, wx) float64, x fastest.  The state is (27, wy, wx): f, g, hbar.
+    """
+
+    def __init__(self, params: dict, Twall_bot=None, Twall_top=None,
+                 window=None):
+        self.params = dict(params)
+        self.P = _make_params(params, window)
+        self.wx, self.wy = self.P.wx, self.P.wy
+        nx = self.P.NX
+        tb = np.ascontiguousarray(
+            np.zeros(nx) if Twall_bot is None else Twall_bot, dtype=np.float64)
+        tt = np.ascontiguousarray(
+            np.zeros(nx) if Twall_top is None else Twall_top, dtype=np.float64)
+        assert tb.shape == (nx,) and tt.shape == (nx,)
+        self._h = lib().orc_create(ctypes.byref(self.P), _ptr(tb), _ptr(tt))
+        if not self._h:
+            raise ValueError("oracle: invalid grid")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    def _field(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        assert a.shape == (self.wy, self.wx), a.shape
+        return a
+
+    def init(self, phi0, T0):
+        lib().orc_init(self._h, _ptr(self._field(phi0)), _ptr(self._field(T0)))
+        return self
+
+    def set_state(self, F):
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        assert F.shape == (27, self.wy, self.wx)
+        lib().orc_set_state(self._h, _ptr(F))
+        return self
+
+    def state(self):
+        F = np.zeros((27, self.wy, self.wx))
+        lib().orc_get_state(self._h, _ptr(F))
+        return F
+
+    def step(self, n: int = 1):
+        lib().orc_step(self._h, int(n))
+        return self
+
+    def fields(self):
+        out = [np.zeros((self.wy, self.wx)) for _ in range(5)]
+        lib().orc_fields(self._h, *[_ptr(a) for a in out])
+        return dict(zip(("phi", "ux", "uy", "p", "T"), out))
+
+    def intermediates(self):
+        out = np.zeros((17, self.wy, self.wx))
+        lib().orc_intermediates(self._h, _ptr(out))
+        return dict(zip(INTERMEDIATE_KEYS, out))
+
+    def diag(self):
+        d = np.zeros(N_DIAG)
+        lib().orc_diag(self._h, _ptr(d))
+        out = dict(zip(DIAG_KEYS, d))
+        out["n_nonfinite"] = int(out["n_nonfinite"])
+        out["centroid_y"] = out["sum_cy"] / out["mass"] if out["mass"] else float("nan")
+        out["u_r"] = (out["sum_cuy_thr"] / out["mass_thr"]
+                      if out["mass_thr"] else float("nan"))
+        return out

@@ -1,0 +1,276 @@
+"""Seeded synthetic inputs: parameter sets and initial fields of the workloads.
+
+This module only generates inputs (parameters, initial order parameter and
+temperature fields, wall temperatures, random states for parity checks).  It
+holds none of the lattice Boltzmann arithmetic: both the HIP library and the
+CPU oracle receive exactly these arrays and derive everything else on their
+own.
+
+The workloads are the paper's three validation problems (Sec. IV) at the
+sizes of the build's benchmark set, plus a large multi-droplet throughput
+case and a differentiated droplet case:
+
+  poiseuille        8 x 64      thermal two-layer Poiseuille flow (Sec. IV A)
+  planar_marangoni  256 x 128   two superimposed planar fluids (Sec. IV B)
+  droplet           512 x 1024  one migrating droplet (Sec. IV C)
+  adjoint_droplet   256 x 512   droplet case differentiated w.r.t. sigmaT, T_wall
+  multi_droplet     4096 x 4096 200 seeded droplets, throughput
+
+Grid convention: sites (i, j) at x = i + 1/2, y = j + 1/2; x periodic; when
+``walls_y`` is 1 the walls sit halfway, at y = 0 and y = ny.  Arrays are
+(ny, nx) float64, x fastest.  phi = 2c - 1 with c = 1 inside droplets and in
+the upper layer.
+
+Relaxation times are stated directly; the comments give the transport
+coefficients they stand for (eta = (tau_f - 1/2)/3, lambda = (tau_T - 1/2)/3
+at rho = cv = 1).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+W_DEFAULT = 2.0 * math.sqrt(2.0)   # tanh width for eps = 1 at beta = 1/4
+
+PARAM_KEYS = ("nx", "ny", "walls_y", "rho", "cv", "tau_f", "tau_T", "tau_g",
+              "mobility", "width", "beta", "sigma0", "sigmaT", "Tref", "force",
+              "p0", "T_shift")
+
+WORKLOADS = ("poiseuille", "planar_marangoni", "droplet", "adjoint_droplet",
+             "multi_droplet")
+
+
+def base_params(nx: int, ny: int, **kw) -> dict:
+    p = dict(nx=nx, ny=ny, walls_y=1, rho=1.0, cv=1.0, tau_f=(1.0, 1.0),
+             tau_T=(1.0, 1.0), tau_g=1.0, mobility=0.05, width=W_DEFAULT,
+             beta=0.25, sigma0=1e-2, sigmaT=0.0, Tref=0.0, force=(0.0, 0.0),
+             p0=1.0 / 3.0, T_shift=0.0)
+    p.update(kw)
+    return p
+
+
+def coords(nx: int, ny: int):
+    """Site centre coordinates (Y, X), each (ny, nx)."""
+    y = np.arange(ny, dtype=np.float64) + 0.5
+    x = np.arange(nx, dtype=np.float64) + 0.5
+    return np.meshgrid(y, x, indexing="ij")
+
+
+def tanh_layer(nx, ny, y_if, width, upper_is_one=True):
+    Y, _ = coords(nx, ny)
+    s = 1.0 if upper_is_one else -1.0
+    return np.tanh(s * (Y - y_if) / width)
+
+
+def droplet_phi(nx, ny, drops, width, periodic_x=True):
+    """phi for droplets [(xc, yc, R), ...]: c = max_k 1/2 + 1/2 tanh((R_k - r_k)/W).
+
+    Each droplet is evaluated on its bounding box (R + 64 lattice units, where
+    the tanh tail is below 1e-19); phi = -1 elsewhere."""
+    phi = -np.ones((ny, nx))
+    for xc, yc, R in drops:
+        m = int(math.ceil(R + 64))
+        j0, j1 = max(0, int(yc) - m), min(ny, int(yc) + m + 1)
+        ii = np.arange(int(xc) - m, int(xc) + m + 1)
+        if periodic_x:
+            cols = np.mod(ii, nx)
+            if len(ii) >= nx:
+                ii = np.arange(nx)
+                cols = ii
+        else:
+            ii = ii[(ii >= 0) & (ii < nx)]
+            cols = ii
+        y = np.arange(j0, j1) + 0.5
+        x = ii + 0.5
+        dx = x[None, :] - xc
+        if periodic_x:
+            dx = (dx + nx / 2.0) % nx - nx / 2.0
+        r = np.sqrt(dx ** 2 + (y[:, None] - yc) ** 2)
+        val = np.tanh((R - r) / width)
+        sub = phi[j0:j1][:, cols]
+        phi[j0:j1, cols] = np.maximum(sub, val)
+    return phi
+
+
+def place_droplets(nx, ny, n_drops, seed, rmin, rmax, gap=8.0,
+                   max_tries=200000):
+    """Seeded non-overlapping droplets: R ~ U[rmin, rmax], x ~ U[0, nx),
+    y ~ U[R + gap, ny - R - gap]; a candidate is rejected if it comes closer
+    than R_a + R_b + gap to a placed one (x distance periodic)."""
+    rng = np.random.default_rng(seed)
+    drops = []
+    tries = 0
+    while len(drops) < n_drops:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place droplets")
+        R = rng.uniform(rmin, rmax)
+        x = rng.uniform(0.0, nx)
+        y = rng.uniform(R + gap, ny - R - gap)
+        ok = True
+        for (xb, yb, Rb) in drops:
+            dx = abs(x - xb)
+            dx = min(dx, nx - dx)
+            if math.hypot(dx, y - yb) < R + Rb + gap:
+                ok = False
+                break
+        if ok:
+            drops.append((x, y, R))
+    return drops
+
+
+# ---- steady conduction field between the walls (adjoint_droplet) -------------
+def _conduction_kernel(nx, ny):
+    """B[j, m]: response at row j of wall mode m (rfft order) of the bottom
+    wall, for Laplace's equation with the top wall held at 0.  Mode 0 is
+    linear, mode m is sinh(k (ny - y)) / sinh(k ny), written in overflow-free
+    exponential form."""
+    y = np.arange(ny, dtype=np.float64) + 0.5
+    m = np.arange(nx // 2 + 1, dtype=np.float64)
+    k = 2.0 * np.pi * m / nx
+    B = np.empty((ny, m.size))
+    B[:, 0] = 1.0 - y / ny
+    kk = k[None, 1:]
+    yy = y[:, None]
+    B[:, 1:] = (np.exp(-kk * yy) * (1.0 - np.exp(-2.0 * kk * (ny - yy)))
+                / (1.0 - np.exp(-2.0 * kk * ny)))
+    return B
+
+
+def conduction_field(Tw_bot, T_top, ny):
+    """T0 solving Laplace's equation, periodic in x, T = Tw_bot on y = 0 and
+    T = T_top on y = ny (linear in (Tw_bot, T_top))."""
+    Tw_bot = np.asarray(Tw_bot, dtype=np.float64)
+    nx = Tw_bot.size
+    B = _conduction_kernel(nx, ny)
+    Fw = np.fft.rfft(Tw_bot)
+    T = np.fft.irfft(Fw[None, :] * B, n=nx, axis=1)
+    y = np.arange(ny, dtype=np.float64) + 0.5
+    return T + (T_top * y / ny)[:, None]
+
+
+def conduction_field_T(G, ny):
+    """Transpose of ``conduction_field`` w.r.t. Tw_bot: given G = dJ/dT0
+    (ny, nx) returns dJ/dTw_bot (nx,).  Each row map is a symmetric circulant,
+    so the transpose applies the same kernel."""
+    G = np.asarray(G, dtype=np.float64)
+    nx = G.shape[1]
+    B = _conduction_kernel(nx, ny)
+    return np.fft.irfft(np.fft.rfft(G, axis=1) * B, n=nx, axis=1).sum(axis=0)
+
+
+# ---- the workloads -----------------------------------------------------------
+def _droplet_physics(**kw):
+    # eta = 0.0715542, lambda = 7.15542e-3: Re = 1 and Ma = 10 for R = 32,
+    # sigmaT = 5e-4, |grad T| = 0.01 (U = sigmaT |grad T| R / eta)
+    return dict(tau_f=(0.7146625, 0.7146625), tau_T=(0.5214663, 0.5214663),
+                tau_g=1.0, mobility=0.05, width=W_DEFAULT, beta=0.25,
+                sigma0=1e-2, sigmaT=5e-4, Tref=0.0, **kw)
+
+
+def make(name: str, **overrides) -> dict:
+    """Return dict(params, phi0, T0, Twall_bot, Twall_top, nsteps, precision,
+    meta) for a named workload.  ``overrides`` replace parameter entries."""
+    if name == "poiseuille":
+        nx, ny = 8, 64
+        # eta 0.1 / 0.3 (1:3), lambda 0.1 / 0.2 (1:2); c = 0 lower layer
+        p = base_params(nx, ny, tau_f=(0.8, 1.4), tau_T=(0.8, 1.1), tau_g=2.5,
+                        mobility=0.1, width=4.0, sigma0=1e-3, sigmaT=1e-4,
+                        Tref=10.0, force=(1e-6, 0.0), T_shift=15.0)
+        phi0 = tanh_layer(nx, ny, ny / 2, 4.0)
+        Y, _ = coords(nx, ny)
+        T0 = 20.0 - 10.0 * Y / ny
+        tb, tt = np.full(nx, 20.0), np.full(nx, 10.0)
+        nsteps, prec = 20000, "fp64"
+    elif name == "planar_marangoni":
+        nx, ny = 256, 128
+        # eta = lambda = 0.2 in both fluids; Re = Ma = 1e-3 (U_max = 3.125e-6)
+        p = base_params(nx, ny, tau_f=(1.1, 1.1), tau_T=(1.1, 1.1), tau_g=1.0,
+                        mobility=5e-2, width=W_DEFAULT, sigma0=2.5e-2,
+                        sigmaT=4.661e-6, Tref=10.0, T_shift=10.0)
+        phi0 = tanh_layer(nx, ny, ny / 2, W_DEFAULT)
+        T0 = np.full((ny, nx), 10.0)
+        x = np.arange(nx) + 0.5
+        tb = 10.0 + 4.0 * np.cos(2.0 * np.pi * x / nx)
+        tt = np.full(nx, 10.0)
+        nsteps, prec = 50000, "fp32_dev"
+    elif name == "droplet":
+        nx, ny = 512, 1024
+        p = base_params(nx, ny, T_shift=5.12, **_droplet_physics())
+        phi0 = droplet_phi(nx, ny, [(256.0, 128.0, 32.0)], W_DEFAULT)
+        Y, _ = coords(nx, ny)
+        T0 = 0.01 * Y
+        tb, tt = np.zeros(nx), np.full(nx, 0.01 * ny)
+        nsteps, prec = 100000, "fp32_dev"
+    elif name == "adjoint_droplet":
+        nx, ny = 256, 512
+        p = base_params(nx, ny, T_shift=2.56, **_droplet_physics())
+        phi0 = droplet_phi(nx, ny, [(128.0, 96.0, 24.0)], W_DEFAULT)
+        rng = np.random.default_rng(6238)
+        tb = 0.0 + rng.normal(0.0, 0.1, nx)
+        tt = np.full(nx, 0.01 * ny)
+        T0 = conduction_field(tb, tt[0], ny)
+        nsteps, prec = 4000, "fp32_dev"
+    elif name == "multi_droplet":
+        nx, ny = 4096, 4096
+        p = base_params(nx, ny, T_shift=4.096, **_droplet_physics())
+        drops = place_droplets(nx, ny, 200, 1412, 16.0, 48.0)
+        phi0 = droplet_phi(nx, ny, drops, W_DEFAULT)
+        Y, _ = coords(nx, ny)
+        T0 = 0.002 * Y
+        tb, tt = np.zeros(nx), np.full(nx, 0.002 * ny)
+        nsteps, prec = 2000, "fp32_dev"
+    else:
+        raise KeyError(name)
+    p.update(overrides)
+    return dict(params=p, phi0=np.ascontiguousarray(phi0),
+                T0=np.ascontiguousarray(T0), Twall_bot=np.ascontiguousarray(tb),
+                Twall_top=np.ascontiguousarray(tt), nsteps=nsteps,
+                precision=prec, name=name)
+
+
+def random_case(nx, ny, seed, walls_y=1, n_drops=2, amp_T=0.5, **kw):
+    """Small seeded case for parity checks: a few droplets (radius 2-5 sites
+    smaller than the grid), a random temperature field around 1 and random
+    wall temperatures, with parameters drawn in stable ranges."""
+    rng = np.random.default_rng(seed)
+    tau_g = float(rng.uniform(0.8, 1.3))
+    width = float(rng.uniform(1.5, 3.0))
+    # mobility kept below 0.1 (tau_g - 1/2) / eps^2 with eps^2 = W^2 beta / 2:
+    # larger values make the shortest lattice waves of c grow
+    mobility = float(rng.uniform(0.3, 1.0)) * 0.1 * (tau_g - 0.5) / (width ** 2 / 8.0)
+    p = base_params(
+        nx, ny, walls_y=walls_y,
+        tau_f=tuple(rng.uniform(0.6, 1.4, 2)), tau_T=tuple(rng.uniform(0.55, 1.2, 2)),
+        tau_g=tau_g, mobility=mobility, width=width, beta=0.25,
+        sigma0=float(rng.uniform(5e-3, 2e-2)), sigmaT=float(rng.uniform(-2e-3, 2e-3)),
+        Tref=float(rng.uniform(0.5, 1.5)),
+        force=tuple(rng.uniform(-1e-4, 1e-4, 2)), p0=1.0 / 3.0, T_shift=1.0)
+    p.update(kw)
+    drops = []
+    for _ in range(n_drops):
+        R = float(rng.uniform(2.0, max(2.5, min(nx, ny) / 4)))
+        drops.append((float(rng.uniform(0, nx)), float(rng.uniform(0, ny)), R))
+    phi0 = droplet_phi(nx, ny, drops, p["width"])
+    phi0 = np.clip(phi0 + 0.05 * rng.standard_normal((ny, nx)), -1.2, 1.2)
+    T0 = 1.0 + amp_T * rng.standard_normal((ny, nx))
+    tb = 1.0 + 0.3 * rng.standard_normal(nx)
+    tt = 1.0 + 0.3 * rng.standard_normal(nx)
+    return dict(params=p, phi0=np.ascontiguousarray(phi0), T0=np.ascontiguousarray(T0),
+                Twall_bot=tb, Twall_top=tt, name=f"random_{nx}x{ny}_s{seed}")
+
+
+def random_state(nx, ny, seed, p0=1.0 / 3.0, T=1.0):
+    """A seeded non-equilibrium state (27, ny, nx): rest-weight values with
+    10% relative noise for f and hbar, and order-parameter populations that
+    sum to a c field in [-0.1, 1.1]."""
+    rng = np.random.default_rng(seed)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    F = np.empty((27, ny, nx))
+    F[0:9] = w[:, None, None] * p0 * (1.0 + 0.1 * rng.standard_normal((9, ny, nx)))
+    cfield = rng.uniform(-0.1, 1.1, (ny, nx))
+    gn = 0.02 * rng.standard_normal((9, ny, nx))
+    F[9:18] = w[:, None, None] * cfield[None] + gn
+    F[18:27] = w[:, None, None] * T * (1.0 + 0.1 * rng.standard_normal((9, ny, nx)))
+    return F

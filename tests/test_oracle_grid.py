@@ -1,0 +1,250 @@
+"""Pins of the oracle's grid passes: stencils, boundary rules, invariants,
+windows, and the exact one-step response of single lattice modes.
+
+Each check is fixed by something other than the oracle itself: polynomial
+exactness of the stencils, conservation laws, mirror symmetry, the exact
+linear algebra of one step for a single Fourier mode (derived by hand from
+the equilibria of Sec. II Eqs. 13-14 and Sec. III Eq. 22), and the uniform-
+force momentum budget that decides the half-force reading of Eq. 9.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1412_6238_amd import workloads as wl
+
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def _state_from_fields(c, T, p, rho_cv=1.0):
+    """A state whose moments are (c, T, p) with zero momentum."""
+    ny, nx = c.shape
+    F = np.zeros((27, ny, nx))
+    F[0] = p
+    F[9] = c
+    F[18] = rho_cv * T
+    return F
+
+
+# ---- stencils ------------------------------------------------------------------
+def test_stencils_exact_on_quadratics(oracle_mod):
+    """grad and lap are exact for quadratic fields (interior of a window)."""
+    NX = NY = 1000
+    x0, y0, wx, wy = 100, 200, 12, 10
+    p = wl.base_params(NX, NY, walls_y=0)
+    o = oracle_mod.Oracle(p, window=(x0, y0, wx, wy))
+    y = np.arange(y0, y0 + wy) + 0.5
+    x = np.arange(x0, x0 + wx) + 0.5
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    # coefficients chosen so that values stay O(1) at x, y ~ 100
+    c = 0.3 + 1e-3 * X - 2e-3 * Y + 1e-5 * X ** 2 - 3e-5 * X * Y + 2e-5 * Y ** 2
+    T = 2.0 - 1e-3 * X + 4e-3 * Y + 3e-5 * X ** 2 + 1e-5 * X * Y - 1e-5 * Y ** 2
+    pr = 0.33 + 2e-4 * X + 1e-4 * Y
+    o.set_state(_state_from_fields(c, T, pr))
+    I = o.intermediates()
+    inner = (slice(1, -1), slice(1, -1))
+    np.testing.assert_allclose(I["gcx"][inner], (1e-3 + 2e-5 * X - 3e-5 * Y)[inner], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(I["gcy"][inner], (-2e-3 - 3e-5 * X + 4e-5 * Y)[inner], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(I["lapc"][inner], 2e-5 + 4e-5, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(I["gTx"][inner], (-1e-3 + 6e-5 * X + 1e-5 * Y)[inner], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(I["gTy"][inner], (4e-3 + 1e-5 * X - 2e-5 * Y)[inner], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(I["gpx"][inner], 2e-4, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(I["gpy"][inner], 1e-4, rtol=0, atol=1e-14)
+    # every site on the window edge depends on unknown neighbours
+    edge = np.ones((wy, wx), bool)
+    edge[inner] = False
+    assert np.all(np.isnan(I["gcx"][edge]))
+    assert np.all(np.isfinite(I["gcx"][inner]))
+
+
+def test_wall_ghosts(oracle_mod):
+    """Mirror ghosts make lap c exact for fields even about the wall; the
+    temperature ghost 2 T_w - T makes grad T exact for T linear in y with
+    T = T_w on the wall (bottom wall at y = 0, top wall at y = ny)."""
+    nx, ny = 10, 12
+    p = wl.base_params(nx, ny, walls_y=1)
+    Y, X = wl.coords(nx, ny)
+    Tw_b, Tw_t, G = 1.5, 1.5 + 0.7 * ny, 0.7
+    o = oracle_mod.Oracle(p, np.full(nx, Tw_b), np.full(nx, Tw_t))
+    kx = 2 * math.pi / nx
+    c = 0.2 + 0.01 * Y ** 2 + 0.05 * np.cos(kx * X)          # even about y = 0
+    T = Tw_b + G * Y
+    o.set_state(_state_from_fields(c, T, np.full_like(c, 0.3)))
+    I = o.intermediates()
+    lap_x = 0.05 * (2 * np.cos(kx) - 2) * np.cos(kx * X)        # lattice symbol along x
+    # rows 0..ny-2 see the bottom mirror only; y^2 is exact there
+    # (x part: the 9-point Laplacian of cos(kx x) at ky = 0 is (2 cos k - 2) cos)
+    np.testing.assert_allclose(I["lapc"][:-1], (0.02 + lap_x)[:-1], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(I["gTy"], G, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(I["gTx"], 0.0, rtol=0, atol=1e-13)
+    # the top ghost mirrors row ny-1 too: c even about y = ny
+    c2 = 0.2 + 0.01 * (Y - ny) ** 2
+    o.set_state(_state_from_fields(c2, T, np.full_like(c, 0.3)))
+    I = o.intermediates()
+    np.testing.assert_allclose(I["lapc"][1:], 0.02, rtol=0, atol=1e-13)
+    # grad p across a wall row vanishes for a p that is even about the wall
+    np.testing.assert_allclose(I["gpy"], 0.0, atol=1e-15)
+
+
+# ---- invariants ------------------------------------------------------------------
+@pytest.mark.parametrize("walls_y", [0, 1])
+def test_order_parameter_mass_conserved(oracle_mod, walls_y):
+    """sum c is conserved by collision (zero-moment source) and by streaming
+    with bounce-back, to round-off (Sec. II, Eqs. 12, 15)."""
+    case = wl.random_case(24, 20, seed=11 + walls_y, walls_y=walls_y)
+    o = oracle_mod.Oracle(case["params"], case["Twall_bot"], case["Twall_top"])
+    o.init(case["phi0"], case["T0"])
+    m0 = o.diag()["mass"]
+    o.step(400)
+    d = o.diag()
+    assert d["n_nonfinite"] == 0
+    assert abs(d["mass"] - m0) / abs(m0) < 1e-13
+
+
+def test_periodic_energy_conserved(oracle_mod):
+    """Without walls sum rho cv T is conserved too (Sec. III, Eqs. 25-26)."""
+    case = wl.random_case(16, 16, seed=5, walls_y=0)
+    o = oracle_mod.Oracle(case["params"]).init(case["phi0"], case["T0"])
+    e0 = o.diag()["energy"]
+    o.step(300)
+    assert abs(o.diag()["energy"] - e0) / abs(e0) < 1e-13
+
+
+def test_uniform_force_momentum_budget(oracle_mod):
+    """In a uniform periodic box the momentum grows by F per step, so with
+    u_0 = F/(2 rho) (zero first moment at start) u_n = (n + 1/2) F / rho.
+    This holds only for the half-force correction (dt/2) cs^2 F in Eq. 9;
+    the literal (dt/2) F would give (1 + omega) F per step."""
+    a = np.array([1e-5, -2e-5])
+    for tau in (0.6, 0.9, 1.7):
+        p = wl.base_params(8, 8, walls_y=0, force=tuple(a), tau_f=(tau, tau), sigma0=0.0)
+        o = oracle_mod.Oracle(p).init(-np.ones((8, 8)), np.ones((8, 8)))
+        for n in (0, 1, 5, 20):
+            if n:
+                o.step(n - o_n)
+            o_n = n
+            f = o.fields()
+            np.testing.assert_allclose(f["ux"], (n + 0.5) * a[0], rtol=1e-11)
+            np.testing.assert_allclose(f["uy"], (n + 0.5) * a[1], rtol=1e-11)
+
+
+def test_mirror_symmetry(oracle_mod):
+    """A droplet centred in x with x-independent walls and temperature keeps c
+    even and u_x odd about the centre line."""
+    nx, ny = 40, 48
+    p = wl.base_params(nx, ny, sigma0=1e-2, sigmaT=1e-3, tau_f=(0.7, 0.9), tau_T=(0.6, 0.8))
+    phi0 = wl.droplet_phi(nx, ny, [(nx / 2, 18.0, 8.0)], p["width"])
+    Y, _ = wl.coords(nx, ny)
+    o = oracle_mod.Oracle(p, np.zeros(nx), np.full(nx, 0.05 * ny)).init(phi0, 0.05 * Y)
+    o.step(200)
+    f = o.fields()
+    np.testing.assert_allclose(f["phi"], f["phi"][:, ::-1], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(f["ux"], -f["ux"][:, ::-1], rtol=0, atol=1e-12 * np.abs(f["ux"]).max())
+    np.testing.assert_allclose(f["uy"], f["uy"][:, ::-1], rtol=0, atol=1e-12 * np.abs(f["uy"]).max())
+    assert np.abs(f["ux"]).max() > 1e-7
+
+
+def test_pressure_gauge_symmetry(oracle_mod):
+    """Shifting the reference pressure shifts every f_i by w_i dp and changes
+    nothing else: f only enters through p (linearly), grad p and u."""
+    case = wl.random_case(20, 16, seed=3)
+    out = []
+    for p0 in (1.0 / 3.0, 0.0):
+        p = dict(case["params"], p0=p0)
+        o = oracle_mod.Oracle(p, case["Twall_bot"], case["Twall_top"]).init(case["phi0"], case["T0"])
+        o.step(60)
+        out.append(o.fields())
+    for k in ("phi", "ux", "uy", "T"):
+        np.testing.assert_allclose(out[0][k], out[1][k], rtol=0,
+                                   atol=1e-11 * max(1.0, np.abs(out[0][k]).max()))
+    np.testing.assert_allclose(out[0]["p"] - out[1]["p"], 1.0 / 3.0, atol=1e-12)
+
+
+# ---- windows ------------------------------------------------------------------------
+def test_window_matches_full_grid(oracle_mod):
+    """A window advanced alone reproduces the full grid bitwise wherever its
+    dependence cone stays inside (2 sites per step, 1 for the initial state);
+    elsewhere (and only there) values are unknown."""
+    case = wl.random_case(32, 24, seed=9, walls_y=1)
+    full = oracle_mod.Oracle(case["params"], case["Twall_bot"], case["Twall_top"])
+    full.init(case["phi0"], case["T0"])
+    x0, y0, wx, wy = 30, 0, 22, 17                    # wraps in x, touches the bottom wall
+    cols = np.arange(x0, x0 + wx) % 32
+    sub = lambda a: a[y0:y0 + wy][:, cols]
+    win = oracle_mod.Oracle(case["params"], case["Twall_bot"], case["Twall_top"],
+                            window=(x0, y0, wx, wy))
+    win.init(sub(case["phi0"]), sub(case["T0"]))
+    for n in range(4):
+        Ff, Fw = full.state(), win.state()
+        # distance from the window's non-wall edges (left, right, top)
+        jj, ii = np.meshgrid(np.arange(wy), np.arange(wx), indexing="ij")
+        dist = np.minimum(np.minimum(ii, wx - 1 - ii), wy - 1 - jj)
+        valid = dist >= 1 + 2 * n
+        for k in range(27):
+            np.testing.assert_array_equal(Fw[k][valid], sub(Ff[k])[valid])
+        assert np.all(np.isnan(Fw[:, ~valid].sum(axis=0)))
+        full.step(1)
+        win.step(1)
+
+
+# ---- exact one-step response of single lattice modes -----------------------------
+def _lap_symbol(kx, ky):
+    """Eigenvalue of the nine-point Laplacian on exp(i (kx x + ky y))."""
+    return (4 / 3) * (math.cos(kx) + math.cos(ky) - 2) + (2 / 3) * (math.cos(kx) * math.cos(ky) - 1)
+
+
+@pytest.mark.parametrize("mode", [(1, 0), (0, 3), (2, 5), (8, 8), (0, 8), (4, 1)])
+def test_cahn_hilliard_mode_factor(oracle_mod, mode):
+    """With tau_g = 1 the order-parameter LBE forgets its non-equilibrium part,
+    so one step maps c to sum_i g^eq_i(x - xi_i) = c + (Gamma/2) lap(mu)
+    (Eqs. 13-14; M = Gamma (tau_g - 1/2), Eq. 16).  Linearised about c = 0,
+    mu = 2 beta c - eps^2 lap c, so a mode with Laplacian symbol L grows by
+    1 + M L (2 beta - eps^2 L) per step."""
+    n = 16
+    kx, ky = 2 * math.pi * mode[0] / n, 2 * math.pi * mode[1] / n
+    for W, M, beta in ((2 * math.sqrt(2), 0.05, 0.25), (4.0, 0.1, 0.25), (2.0, 0.02, 0.7)):
+        p = wl.base_params(n, n, walls_y=0, tau_g=1.0, mobility=M, width=W, beta=beta,
+                           sigma0=1e-2, sigmaT=0.0)
+        eps2 = W * W * beta / 2
+        Y, X = wl.coords(n, n)
+        delta = 1e-7
+        c0 = delta * np.cos(kx * X + ky * Y)
+        o = oracle_mod.Oracle(p).init(2 * c0 - 1, np.ones((n, n)))
+        o.step(1)
+        c1 = (o.fields()["phi"] + 1) / 2
+        L = _lap_symbol(kx, ky)
+        r = 1 + M * L * (2 * beta - eps2 * L)
+        np.testing.assert_allclose(c1, r * c0, rtol=0, atol=1e-6 * delta * max(1, abs(r)))
+
+
+def test_cahn_hilliard_unstable_mode_matches_prediction(oracle_mod):
+    """The same factor predicts the checkerboard blow-up at M = 0.1, W = 4,
+    tau_g = 1 (|r| > 1), which is why the Poiseuille workload uses tau_g = 2.5."""
+    n = 8
+    p = wl.base_params(n, n, walls_y=0, tau_g=1.0, mobility=0.1, width=4.0, sigma0=0.0)
+    Y, X = wl.coords(n, n)
+    c0 = 1e-9 * np.cos(math.pi * X + math.pi * Y)
+    o = oracle_mod.Oracle(p).init(2 * c0 - 1, np.ones((n, n)))
+    o.step(3)
+    c3 = (o.fields()["phi"] + 1) / 2
+    L = _lap_symbol(math.pi, math.pi)
+    r = 1 + 0.1 * L * (0.5 - 2.0 * L)
+    assert r < -1
+    np.testing.assert_allclose(c3, r ** 3 * c0, rtol=1e-5, atol=1e-20)
+
+
+@pytest.mark.parametrize("mode", [(1, 0), (3, 2), (8, 8)])
+def test_thermal_mode_factor(oracle_mod, mode):
+    """With tau_T = 1 and u = 0, Eqs. 22, 25, 26 give
+    T_{n+1}(x) = sum_i w_i T_n(x - xi_i): a mode is multiplied by
+    4/9 + 2/9 (cos kx + cos ky) + 1/9 cos kx cos ky."""
+    n = 16
+    kx, ky = 2 * math.pi * mode[0] / n, 2 * math.pi * mode[1] / n
+    p = wl.base_params(n, n, walls_y=0, tau_T=(1.0, 1.0), sigma0=0.0, cv=1.7, rho=1.3)
+    Y, X = wl.coords(n, n)
+    T0 = 2.0 + 0.1 * np.cos(kx * X + ky * Y)
+    o = oracle_mod.Oracle(p).init(-np.ones((n, n)), T0)
+    o.step(2)
+    r = 4 / 9 + 2 / 9 * (math.cos(kx) + math.cos(ky)) + 1 / 9 * math.cos(kx) * math.cos(ky)
+    np.testing.assert_allclose(o.fields()["T"] - 2.0, r ** 2 * (T0 - 2.0), rtol=0, atol=1e-14)

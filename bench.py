@@ -1,0 +1,159 @@
+"""Benchmark of the fused CSF lattice Boltzmann step on one MI355X.
+
+A step is one pass of the whole path (three coupled D2Q9 lattices: stream,
+moments, stencils, CSF force, three collisions, and the FP64 diagnostics
+every --diag-every steps) over the 4096 x 4096 multi-droplet workload
+(200 seeded droplets, R in [16, 48], dT/dy = 0.002), with every input already
+resident in HBM.  Metric: million lattice updates per second (all three
+lattices at one site = one update).  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps 2000] [--warmup 10] [--precision fp32_dev]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_SITE = {"fp32_dev": 216, "fp64": 432}   # 27 values read + 27 written
+KERNEL_SOURCES = ("paper_1412_6238_amd/csrc/step_kernel.h", "paper_1412_6238_amd/csrc/lattice.h")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload, precision, sites):
+    """Measured HBM bytes per launch from the committed counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(w, seconds=15.0):
+    """The FP64 oracle on the host cores, on a band of the same workload
+    (the lowest 512 rows, full width, with the bottom wall), timed for about
+    `seconds`; MLUPS over the band's sites."""
+    import numpy as np
+    from oracle import oracle
+    p = w["params"]
+    nx = p["nx"]
+    rows = min(512, p["ny"])
+    win = (0, 0, nx, rows)
+    o = oracle.Oracle(p, w["Twall_bot"], w["Twall_top"], window=win)
+    o.init(np.ascontiguousarray(w["phi0"][:rows]), np.ascontiguousarray(w["T0"][:rows]))
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter()
+    n = max(1, int((seconds - (t1 - t0)) / max(t1 - t0, 1e-3)))
+    o.step(n)
+    t2 = time.perf_counter()
+    steps = n + 1
+    mlups = nx * rows * steps / (t2 - t0) / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, rows 0-{rows - 1} of the {nx}x{p['ny']} workload "
+                      f"({nx * rows} sites incl. the bottom wall), {steps} steps, "
+                      f"{t2 - t0:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", default="fp32_dev", choices=("fp32_dev", "fp64"))
+    ap.add_argument("--workload", default="multi_droplet")
+    ap.add_argument("--diag-every", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "slab decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1412_6238_amd import lbe_csf, workloads as wl
+
+    w = wl.make(args.workload)
+    p = w["params"]
+    nx, ny = p["nx"], p["ny"]
+    sites = nx * ny
+    sim = lbe_csf.Simulation(p, w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"],
+                             precision=args.precision, diag_every=args.diag_every)
+    stream = sim.stream
+    torch.cuda.synchronize()
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    sim.step(args.steps)          # ends with one synchronising check of the diagnostics
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    ms_per_step = ms / args.steps
+    mlups = sites * args.steps / (ms / 1e3) / 1e6
+    hist = sim.diag_history()
+    d_last = sim.diagnostics()
+    mass_drift = None
+    if hist:
+        mass_drift = d_last["mass"] / hist[0]["mass"] - 1.0
+
+    # dominant kernel: the fused step; its average launch time over the timed
+    # region (the region also holds steps/diag_every tiny reduction launches)
+    bps = BYTES_PER_SITE[args.precision]
+    achieved = bps * sites / (ms_per_step / 1e3) / 1e9
+    traffic = traffic_from_profile(args.workload, args.precision, sites)
+    out = {
+        "metric": "MLUPS (3 coupled D2Q9 lattices)",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32_dev" else "f64",
+        "data": "synthetic (seeded droplets, linear temperature)",
+        "config": {"workload": f"{args.workload} {nx}x{ny}", "precision": args.precision,
+                   "sites": sites, "diag_every": args.diag_every,
+                   "bytes_per_site_update": bps},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic},
+        "wall_s": round(wall, 3),
+        "mass_drift": mass_drift,
+        "n_nonfinite": d_last["n_nonfinite"],
+        "kernel_hash": kernel_hash(),
+    }
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -39,6 +39,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ---- D2Q9 lattice (implied by the weights of Eqs. 7, 8, 13, 14) ----------- */
 #define NQ 9
@@ -373,6 +376,15 @@ static void derive(orc *o) {
 }
 
 OAPI int orc_sizeof_params(void) { return (int)sizeof(orc_params); }
+
+/* Number of OpenMP threads the per-site passes use (1 without OpenMP). */
+OAPI int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 OAPI orc *orc_create(const orc_params *P, const double *Twall_bot,
                      const double *Twall_top) {

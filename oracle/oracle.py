@@ -78,6 +78,7 @@ def lib():
         L.orc_collide_site.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp]
         L.orc_derived.argtypes = [ctypes.POINTER(_Params), dp]
         L.orc_sizeof_params.restype = ctypes.c_int
+        L.orc_threads.restype = ctypes.c_int
         assert L.orc_sizeof_params() == ctypes.sizeof(_Params)
         _lib = L
     return _lib
@@ -106,6 +107,11 @@ def _make_params(p: dict, window=None) -> _Params:
     P.force[0], P.force[1] = map(float, p["force"])
     P.p0 = float(p["p0"])
     return P
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's passes run on."""
+    return int(lib().orc_threads())
 
 
 def derived(p: dict) -> dict:

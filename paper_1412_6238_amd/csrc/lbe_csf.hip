@@ -1,0 +1,541 @@
+// lbe_csf.hip -- host side of liblbe_csf.so: parameter checks, workspace
+// layout, launch configuration and the C ABI declared in include/lbe_csf.h.
+//
+// The library owns no device memory: every buffer is carved out of the
+// caller's workspace.  Layout (each region 256-byte aligned):
+//   state A, state B     25 planes (FP64, or FP32 deviations) + FP64 g_0, hbar_0
+//   wall temperatures    2 * nx FP64 (bottom, top)
+//   partials             max blocks * 7 FP64 (per-block diagnostic sums)
+//   diag ring            4096 records of (step, 7 sums)
+//   counters             records written, non-finite total
+//   one record           target of synchronous diagnostics
+//   adjoint region       present when record_steps > 0 (see adjoint.h)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lbe_csf.h"
+#include "adjoint.h"
+#include "aux_kernels.h"
+#include "step_kernel.h"
+
+using namespace lbe;
+
+namespace {
+
+constexpr int kDiagRing = 4096;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Launch {
+  int pipe;      // row pipeline of the step kernel (see step_kernel.h)
+  int nw;        // waves per block (strip width 64 * nw)
+  int nstrips;
+  int rows;      // rows per chunk
+  int nchunks;
+  int nblocks;
+};
+
+Launch pick_launch(int nx, int ny, size_t state_bytes) {
+  Launch L;
+  L.pipe = 1;
+  if (const char *e = std::getenv("LBE_CSF_PIPE")) {
+    const int v = std::atoi(e);
+    if (v == 0 || v == 1 || v == 3) L.pipe = v;
+  }
+  // the LDS-fed kernel moves 16-byte chunks (x a multiple of 4 keeps them
+  // aligned) through one buffer descriptor (state below 4 GiB)
+  if (L.pipe == 3 && (nx % 4 != 0 || state_bytes >= (size_t(1) << 32))) L.pipe = 1;
+  L.nw = nx >= 2048 ? 4 : (nx >= 512 ? 2 : 1);
+  if (L.pipe == 3) L.nw = 1;
+  if (const char *e = std::getenv("LBE_CSF_NW")) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || (v == 4 && L.pipe != 3)) L.nw = v;
+  }
+  const int bx = 64 * L.nw;
+  L.nstrips = (nx + bx - 1) / bx;
+  long long want = (2048LL + L.nstrips - 1) / L.nstrips;  // chunks for >= 2048 blocks
+  int rows = (int)std::max<long long>(4, (ny + want - 1) / want);
+  if (const char *e = std::getenv("LBE_CSF_ROWS")) {
+    const int v = std::atoi(e);
+    if (v >= 1) rows = v;
+  }
+  L.rows = std::min(rows, ny);
+  L.nchunks = (ny + L.rows - 1) / L.rows;
+  L.nblocks = L.nstrips * L.nchunks;
+  return L;
+}
+
+struct Layout {
+  size_t state_bytes;
+  size_t off_a, off_b, off_tw, off_part, off_ring, off_cnt, off_rec, off_adj, total;
+  AdjLayout adj;
+};
+
+bool params_valid(const lbe_csf_params *p, std::string *why) {
+  auto bad = [&](const char *m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (!p) return bad("params is NULL");
+  if (p->nx < 3 || p->ny < 3) return bad("nx and ny must be >= 3");
+  if ((long long)p->nx * p->ny * 27LL >= (1LL << 40)) return bad("grid too large");
+  if (p->walls_y != 0 && p->walls_y != 1) return bad("walls_y must be 0 or 1");
+  if (p->precision != LBE_CSF_FP64 && p->precision != LBE_CSF_FP32_DEV)
+    return bad("unknown precision");
+  auto fin = [](double v) { return std::isfinite(v); };
+  if (!(p->rho > 0) || !(p->cv > 0) || !fin(p->rho) || !fin(p->cv)) return bad("rho and cv must be > 0");
+  for (int k = 0; k < 2; ++k) {
+    if (!(p->tau_f[k] > 0.5) || !fin(p->tau_f[k])) return bad("tau_f must be > 1/2");
+    if (!(p->tau_T[k] > 0.5) || !fin(p->tau_T[k])) return bad("tau_T must be > 1/2");
+  }
+  if (!(p->tau_g > 0.5) || !fin(p->tau_g)) return bad("tau_g must be > 1/2");
+  if (!(p->mobility > 0) || !fin(p->mobility)) return bad("mobility must be > 0");
+  if (!(p->width > 0) || !fin(p->width)) return bad("width must be > 0");
+  if (!(p->beta > 0) || !fin(p->beta)) return bad("beta must be > 0");
+  if (!fin(p->sigma0) || !fin(p->sigmaT) || !fin(p->Tref) || !fin(p->force[0]) ||
+      !fin(p->force[1]) || !fin(p->p0) || !fin(p->T_shift))
+    return bad("non-finite parameter");
+  if (p->diag_every < 0) return bad("diag_every must be >= 0");
+  if (p->reserved != 0) return bad("reserved must be 0");
+  return true;
+}
+
+Layout make_layout(const lbe_csf_params *p, int64_t record_steps) {
+  Layout L{};
+  const size_t n = (size_t)p->nx * p->ny;
+  const size_t vb = p->precision == LBE_CSF_FP64 ? 8 : 4;
+  L.state_bytes = kNumS * n * vb + 2 * n * 8;   // 25 planes + FP64 g_0, hbar_0
+  const Launch la = pick_launch(p->nx, p->ny, L.state_bytes);
+  size_t o = 0;
+  L.off_a = o; o = align_up(o + L.state_bytes);
+  L.off_b = o; o = align_up(o + L.state_bytes);
+  L.off_tw = o; o = align_up(o + 2 * (size_t)p->nx * 8);
+  L.off_part = o; o = align_up(o + (size_t)la.nblocks * kNumPartials * 8);
+  L.off_ring = o; o = align_up(o + (size_t)kDiagRing * sizeof(DiagRecord));
+  L.off_cnt = o; o = align_up(o + 4 * sizeof(int64_t));
+  L.off_rec = o; o = align_up(o + sizeof(DiagRecord));
+  L.off_adj = o;
+  L.adj = adj_layout(p->nx, L.state_bytes, la.nblocks, record_steps);
+  o = align_up(o + L.adj.total);
+  L.total = o;
+  return L;
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct lbe_csf {
+  lbe_csf_params P;
+  Layout L;
+  Launch la;
+  hipStream_t stream;
+  char *ws;
+  void *state[2];
+  int cur;
+  int64_t step;
+  double *tw;         // [2][nx]
+  double *partials;
+  DiagRecord *ring;
+  int64_t *counters;
+  DiagRecord *rec;    // one record for synchronous diagnostics
+  int64_t record_cap;
+  // record of the last recorded run
+  bool recorded;
+  int64_t rec_start, rec_steps, rec_K;
+  std::string err;
+  StepArgs base;      // constants filled once
+};
+
+namespace {
+
+int fail(lbe_csf *h, int code, const std::string &msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(h, expr)                                                        \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return fail(h, LBE_CSF_EDEVICE,                                          \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+void fill_constants(lbe_csf *h) {
+  const lbe_csf_params &p = h->P;
+  StepArgs &a = h->base;
+  std::memset(&a, 0, sizeof(a));
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.walls_y = p.walls_y;
+  a.nstrips = h->la.nstrips;
+  a.rows_per_chunk = h->la.rows;
+  a.twb = h->tw;
+  a.twt = h->tw + p.nx;
+  a.rho = p.rho;
+  a.cv = p.cv;
+  a.rcv = p.rho * p.cv;
+  a.tauf0 = p.tau_f[0];
+  a.dtauf = p.tau_f[1] - p.tau_f[0];
+  a.tauT0 = p.tau_T[0];
+  a.dtauT = p.tau_T[1] - p.tau_T[0];
+  a.omg_g = 1.0 / p.tau_g;
+  // interface constants: W is the tanh denominator of the planar profile,
+  // eps = W sqrt(beta/2); alpha = 3 sqrt(2/beta) makes eps alpha int c'^2 = 1
+  const double eps = p.width * std::sqrt(p.beta / 2.0);
+  const double alpha = 3.0 * std::sqrt(2.0 / p.beta);
+  const double Gamma = p.mobility / (p.tau_g - 0.5);
+  a.gam3 = 3.0 * Gamma;
+  a.beta2 = 2.0 * p.beta;
+  a.eps2 = eps * eps;
+  a.kcap = alpha / eps;
+  a.epsalpha = eps * alpha;
+  a.sigma0 = p.sigma0;
+  a.sigmaT = p.sigmaT;
+  a.Tref = p.Tref;
+  a.ax = p.force[0];
+  a.ay = p.force[1];
+  a.p0 = p.precision == LBE_CSF_FP32_DEV ? p.p0 : 0.0;
+  a.Ts = p.precision == LBE_CSF_FP32_DEV ? p.T_shift : 0.0;
+  a.partials = h->partials;
+}
+
+template <typename S, typename R, bool DEV, int MODE, int PIPE>
+void launch_pipe(const Launch &la, const StepArgs &a, hipStream_t st) {
+  switch (la.nw) {
+    case 1: step_kernel<S, R, DEV, MODE, 1, PIPE><<<la.nblocks, 64, 0, st>>>(a); break;
+    case 2: step_kernel<S, R, DEV, MODE, 2, PIPE><<<la.nblocks, 128, 0, st>>>(a); break;
+    default: step_kernel<S, R, DEV, MODE, 4, PIPE><<<la.nblocks, 256, 0, st>>>(a); break;
+  }
+}
+
+template <typename S, typename R, bool DEV, int MODE>
+void launch_lds(const Launch &la, const StepArgs &a, hipStream_t st) {
+  switch (la.nw) {
+    case 1: step_kernel_lds<S, R, DEV, MODE, 1><<<la.nblocks, 128, 0, st>>>(a); break;
+    default: step_kernel_lds<S, R, DEV, MODE, 2><<<la.nblocks, 192, 0, st>>>(a); break;
+  }
+}
+
+template <typename S, typename R, bool DEV, int MODE>
+void launch_mode(const Launch &la, const StepArgs &a, hipStream_t st) {
+  switch (la.pipe) {
+    case 0: launch_pipe<S, R, DEV, MODE, 0>(la, a, st); break;
+    case 3: launch_lds<S, R, DEV, MODE>(la, a, st); break;
+    default: launch_pipe<S, R, DEV, MODE, 1>(la, a, st); break;
+  }
+}
+
+template <typename S, typename R, bool DEV>
+void launch_prec(int mode, const Launch &la, const StepArgs &a, hipStream_t st) {
+  switch (mode) {
+    case kStore: launch_mode<S, R, DEV, kStore>(la, a, st); break;
+    case kStore | kDiag: launch_mode<S, R, DEV, kStore | kDiag>(la, a, st); break;
+    case kFields: launch_mode<S, R, DEV, kFields>(la, a, st); break;
+    case kDiag: launch_mode<S, R, DEV, kDiag>(la, a, st); break;
+    default: launch_mode<S, R, DEV, kFields | kDiag>(la, a, st); break;
+  }
+}
+
+int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
+                double *ux, double *uy, double *p, double *T) {
+  StepArgs a = h->base;
+  a.src = src;
+  a.dst = dst;
+  a.phi = phi;
+  a.ux = ux;
+  a.uy = uy;
+  a.p = p;
+  a.T = T;
+  if (h->P.precision == LBE_CSF_FP64)
+    launch_prec<double, double, false>(mode, h->la, a, h->stream);
+  else
+    launch_prec<float, float, true>(mode, h->la, a, h->stream);
+  HIPCHK(h, hipGetLastError());
+  return LBE_CSF_OK;
+}
+
+int launch_reduce(lbe_csf *h, int64_t step, bool append) {
+  if (append)
+    diag_reduce_kernel<<<1, 256, 0, h->stream>>>(h->partials, h->la.nblocks, h->ring,
+                                                 kDiagRing, h->counters, step);
+  else
+    diag_reduce_kernel<<<1, 256, 0, h->stream>>>(h->partials, h->la.nblocks, h->rec, 1,
+                                                 nullptr, step);
+  HIPCHK(h, hipGetLastError());
+  return LBE_CSF_OK;
+}
+
+int run_backward(lbe_csf *h, const double *, double *, double *, double *, const double *) {
+  return fail(h, LBE_CSF_EINVAL, "adjoint not available in this build");
+}
+
+void to_public(const DiagRecord &r, lbe_csf_diag *o) {
+  o->step = r.step;
+  o->mass = r.v[0];
+  o->energy = r.v[1];
+  o->sum_cy = r.v[2];
+  o->sum_cx = r.v[3];
+  o->mass_thr = r.v[4];
+  o->sum_cuy_thr = r.v[5];
+  o->centroid_y = r.v[0] != 0.0 ? r.v[2] / r.v[0] : NAN;
+  o->u_r = r.v[4] != 0.0 ? r.v[5] / r.v[4] : NAN;
+  o->n_nonfinite = (int64_t)r.v[6];
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbe_csf_workspace_size(const lbe_csf_params *params, int64_t record_steps,
+                           size_t *bytes) {
+  std::string why;
+  if (!params_valid(params, &why)) return fail(nullptr, LBE_CSF_EINVAL, why);
+  if (!bytes) return fail(nullptr, LBE_CSF_EINVAL, "bytes is NULL");
+  if (record_steps < 0) return fail(nullptr, LBE_CSF_EINVAL, "record_steps < 0");
+  *bytes = make_layout(params, record_steps).total;
+  return LBE_CSF_OK;
+}
+
+int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
+                   int64_t record_steps, void *stream, const double *phi0,
+                   const double *T0, const double *Twall_bot,
+                   const double *Twall_top, lbe_csf **out) {
+  std::string why;
+  if (!out) return fail(nullptr, LBE_CSF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!params_valid(params, &why)) return fail(nullptr, LBE_CSF_EINVAL, why);
+  if (!workspace || !phi0 || !T0) return fail(nullptr, LBE_CSF_EINVAL, "NULL device pointer");
+  if (params->walls_y && (!Twall_bot || !Twall_top))
+    return fail(nullptr, LBE_CSF_EINVAL, "wall temperatures required with walls_y = 1");
+  if (record_steps < 0) return fail(nullptr, LBE_CSF_EINVAL, "record_steps < 0");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(nullptr, LBE_CSF_EINVAL, "workspace not 256-byte aligned");
+  const Layout L = make_layout(params, record_steps);
+  if (bytes < L.total)
+    return fail(nullptr, LBE_CSF_ENOMEM,
+                "workspace too small: need " + std::to_string(L.total) + " bytes");
+  lbe_csf *h = new (std::nothrow) lbe_csf();
+  if (!h) return fail(nullptr, LBE_CSF_ENOMEM, "host allocation failed");
+  h->P = *params;
+  h->L = L;
+  h->la = pick_launch(params->nx, params->ny, L.state_bytes);
+  h->stream = static_cast<hipStream_t>(stream);
+  h->ws = static_cast<char *>(workspace);
+  h->state[0] = h->ws + L.off_a;
+  h->state[1] = h->ws + L.off_b;
+  h->cur = 0;
+  h->step = 0;
+  h->tw = reinterpret_cast<double *>(h->ws + L.off_tw);
+  h->partials = reinterpret_cast<double *>(h->ws + L.off_part);
+  h->ring = reinterpret_cast<DiagRecord *>(h->ws + L.off_ring);
+  h->counters = reinterpret_cast<int64_t *>(h->ws + L.off_cnt);
+  h->rec = reinterpret_cast<DiagRecord *>(h->ws + L.off_rec);
+  h->record_cap = record_steps;
+  h->recorded = false;
+  fill_constants(h);
+  const int nx = params->nx, ny = params->ny;
+  auto cleanup = [&](int rc) {
+    if (rc != LBE_CSF_OK) {
+      g_create_error = h->err;
+      delete h;
+    }
+    return rc;
+  };
+  hipError_t e = hipSuccess;
+  if (params->walls_y) {
+    e = hipMemcpyAsync(h->tw, Twall_bot, nx * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->tw + nx, Twall_top, nx * sizeof(double), hipMemcpyDeviceToDevice,
+                         h->stream);
+  } else {
+    e = hipMemsetAsync(h->tw, 0, 2 * nx * sizeof(double), h->stream);
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(h->counters, 0, 4 * sizeof(int64_t), h->stream);
+  if (e != hipSuccess) {
+    h->err = std::string("copy of wall temperatures: ") + hipGetErrorString(e);
+    return cleanup(LBE_CSF_EDEVICE);
+  }
+  const double beta2 = h->base.beta2, eps2 = h->base.eps2, gam3 = h->base.gam3;
+  dim3 grid((nx + 255) / 256, ny);
+  if (params->precision == LBE_CSF_FP64)
+    init_kernel<double, false><<<grid, 256, 0, h->stream>>>(
+        static_cast<double *>(h->state[0]), phi0, T0, nx, ny, params->walls_y, beta2, eps2,
+        gam3, h->base.rcv, params->p0, 0.0);
+  else
+    init_kernel<float, true><<<grid, 256, 0, h->stream>>>(
+        static_cast<float *>(h->state[0]), phi0, T0, nx, ny, params->walls_y, beta2, eps2,
+        gam3, h->base.rcv, params->p0, params->T_shift);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    h->err = std::string("init kernel: ") + hipGetErrorString(e);
+    return cleanup(LBE_CSF_EDEVICE);
+  }
+  *out = h;
+  return LBE_CSF_OK;
+}
+
+int lbe_csf_step(lbe_csf *h, int64_t nsteps, int32_t record) {
+  if (!h) return LBE_CSF_EINVAL;
+  if (nsteps < 0) return fail(h, LBE_CSF_EINVAL, "nsteps < 0");
+  if (record && (nsteps == 0 || nsteps > h->record_cap))
+    return fail(h, LBE_CSF_EINVAL,
+                "record needs 0 < nsteps <= record_steps of the workspace (" +
+                    std::to_string(h->record_cap) + ")");
+  h->recorded = false;
+  int64_t K = 0;
+  if (record) {
+    K = adj_segment_length(nsteps);
+    h->rec_start = h->step;
+    h->rec_steps = nsteps;
+    h->rec_K = K;
+  }
+  const int de = h->P.diag_every;
+  bool any_diag = false;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    if (record && s % K == 0) {
+      // checkpoint F_{start + s}
+      const int rc = adj_save_checkpoint(h->ws + h->L.off_adj, h->L.adj, s / K,
+                                         h->state[h->cur], h->L.state_bytes, h->stream);
+      if (rc != 0) return fail(h, LBE_CSF_EDEVICE, "checkpoint copy failed");
+    }
+    const bool diag = de > 0 && (h->step % de == 0);
+    int rc = launch_step(h, diag ? (kStore | kDiag) : kStore, h->state[h->cur],
+                         h->state[1 - h->cur], nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (rc != LBE_CSF_OK) return rc;
+    if (diag) {
+      rc = launch_reduce(h, h->step, true);
+      if (rc != LBE_CSF_OK) return rc;
+      any_diag = true;
+    }
+    h->cur = 1 - h->cur;
+    h->step += 1;
+  }
+  if (record) h->recorded = true;
+  if (any_diag) {
+    int64_t cnt[2];
+    HIPCHK(h, hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (cnt[1] > 0) {
+      return fail(h, LBE_CSF_ENONFINITE,
+                  std::to_string(cnt[1]) + " non-finite site values in diagnostics");
+    }
+  }
+  return LBE_CSF_OK;
+}
+
+int lbe_csf_fields(lbe_csf *h, double *phi, double *ux, double *uy, double *p, double *T) {
+  if (!h) return LBE_CSF_EINVAL;
+  return launch_step(h, kFields, h->state[h->cur], nullptr, phi, ux, uy, p, T);
+}
+
+int lbe_csf_diagnostics(lbe_csf *h, lbe_csf_diag *out) {
+  if (!h || !out) return h ? fail(h, LBE_CSF_EINVAL, "out is NULL") : LBE_CSF_EINVAL;
+  int rc = launch_step(h, kDiag, h->state[h->cur], nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr);
+  if (rc != LBE_CSF_OK) return rc;
+  rc = launch_reduce(h, h->step, false);
+  if (rc != LBE_CSF_OK) return rc;
+  DiagRecord r;
+  HIPCHK(h, hipMemcpyAsync(&r, h->rec, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  to_public(r, out);
+  return LBE_CSF_OK;
+}
+
+int lbe_csf_diag_history(lbe_csf *h, lbe_csf_diag *out, int32_t max, int32_t *count) {
+  if (!h) return LBE_CSF_EINVAL;
+  if (!count || (max > 0 && !out)) return fail(h, LBE_CSF_EINVAL, "NULL output");
+  int64_t cnt[2];
+  HIPCHK(h, hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const int64_t have = std::min<int64_t>(cnt[0], kDiagRing);
+  const int64_t ncopy = std::min<int64_t>(have, std::max(0, max));
+  const int64_t first = cnt[0] - have;
+  for (int64_t k = 0; k < ncopy; ++k) {
+    DiagRecord r;
+    HIPCHK(h, hipMemcpyAsync(&r, h->ring + ((first + k) % kDiagRing), sizeof(r),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    to_public(r, &out[k]);
+  }
+  *count = (int32_t)ncopy;
+  int64_t zero[2] = {0, cnt[1]};
+  HIPCHK(h, hipMemcpyAsync(h->counters, zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return LBE_CSF_OK;
+}
+
+int lbe_csf_get_state(lbe_csf *h, double *F) {
+  if (!h) return LBE_CSF_EINVAL;
+  if (!F) return fail(h, LBE_CSF_EINVAL, "F is NULL");
+  const size_t n = (size_t)h->P.nx * h->P.ny;
+  dim3 grid((unsigned)((n + 255) / 256), 27);
+  const double rcvTs = h->base.rcv * h->base.Ts;
+  if (h->P.precision == LBE_CSF_FP64)
+    state_to_f64<double, false><<<grid, 256, 0, h->stream>>>(
+        static_cast<const double *>(h->state[h->cur]), F, h->P.nx, h->P.ny, 0.0, 0.0);
+  else
+    state_to_f64<float, true><<<grid, 256, 0, h->stream>>>(
+        static_cast<const float *>(h->state[h->cur]), F, h->P.nx, h->P.ny, h->base.p0, rcvTs);
+  HIPCHK(h, hipGetLastError());
+  return LBE_CSF_OK;
+}
+
+int lbe_csf_set_state(lbe_csf *h, const double *F) {
+  if (!h) return LBE_CSF_EINVAL;
+  if (!F) return fail(h, LBE_CSF_EINVAL, "F is NULL");
+  const size_t n = (size_t)h->P.nx * h->P.ny;
+  dim3 grid((unsigned)((n + 255) / 256), 27);
+  const double rcvTs = h->base.rcv * h->base.Ts;
+  if (h->P.precision == LBE_CSF_FP64)
+    state_from_f64<double, false><<<grid, 256, 0, h->stream>>>(
+        static_cast<double *>(h->state[h->cur]), F, h->P.nx, h->P.ny, 0.0, 0.0);
+  else
+    state_from_f64<float, true><<<grid, 256, 0, h->stream>>>(
+        static_cast<float *>(h->state[h->cur]), F, h->P.nx, h->P.ny, h->base.p0, rcvTs);
+  HIPCHK(h, hipGetLastError());
+  h->recorded = false;
+  return LBE_CSF_OK;
+}
+
+int64_t lbe_csf_step_count(const lbe_csf *h) { return h ? h->step : -1; }
+
+int lbe_csf_backward(lbe_csf *h, const double *dJ_dc, double *dJ_dsigmaT, double *dJ_dTwall,
+                     double *dJ_dF0, double *dJ_dT0) {
+  if (!h) return LBE_CSF_EINVAL;
+  if (!h->recorded || h->step != h->rec_start + h->rec_steps)
+    return fail(h, LBE_CSF_ENOTRECORDED, "no recorded run ends at the current state");
+  if (!dJ_dc || !dJ_dsigmaT) return fail(h, LBE_CSF_EINVAL, "NULL seed or output");
+  return run_backward(h, dJ_dc, dJ_dsigmaT, dJ_dTwall, dJ_dF0, dJ_dT0);
+}
+
+void lbe_csf_destroy(lbe_csf *h) { delete h; }
+
+const char *lbe_csf_strerror(int status) {
+  switch (status) {
+    case LBE_CSF_OK: return "ok";
+    case LBE_CSF_EINVAL: return "invalid argument";
+    case LBE_CSF_ENOMEM: return "workspace too small";
+    case LBE_CSF_EDEVICE: return "device error";
+    case LBE_CSF_ENOTRECORDED: return "no recorded forward run";
+    case LBE_CSF_ENONFINITE: return "non-finite values in the state";
+    default: return "unknown status";
+  }
+}
+
+const char *lbe_csf_last_error(const lbe_csf *h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

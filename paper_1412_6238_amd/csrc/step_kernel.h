@@ -1,0 +1,694 @@
+// step_kernel.h -- the fused CSF lattice Boltzmann step on gfx950.
+//
+// One launch performs, for every site, the whole step of arXiv:1412.6238:
+//   moments      c = sum g (Eq. 15), rho cv T = sum hbar (Eq. 26),
+//                p = sum f, j = sum xi f                  (Eq. 9)
+//   stencils     grad c, lap c, grad T, grad p (isotropic nine-point; wall
+//                ghosts: c and p mirrored, T_ghost = 2 T_wall - T)
+//   closures     mu = mu0(c) - eps^2 lap c (Eq. 16), sigma(T) (Eq. 5),
+//                CSF force F (Eqs. 3-4 in potential form), u (Eq. 9 with the
+//                half force (1/2) cs^2 F), relaxation rates, Fbar = F - grad p
+//   collisions   f (Eqs. 6-8), g (Eqs. 12-14), hbar (Eqs. 22, 25)
+//   streaming    push to x + xi (x periodic); halfway bounce-back for f, g
+//                and anti-bounce-back with the wall temperature for hbar
+//
+// State layout (structure of arrays, x fastest): 25 planes of the storage
+// type S -- f_0..8, g_1..8, hbar_1..8 -- then two FP64 planes, g_0 and
+// hbar_0.  The rest populations carry the two transported scalars (c = g_0 +
+// small terms, rho cv T = hbar_0 + eight smaller terms); keeping them in FP64
+// keeps c and T accurate to far below FP32 rounding, which matters because c
+// enters the force through eps^2 lap c and T through grad sigma.  The FP32
+// form therefore moves 2 x (25 x 4 + 2 x 8) = 232 bytes per site update.
+//
+// The state held is F_n (pre-collision).  A lane reads the planes of its own
+// site (coalesced, aligned) and pushes post-collision values to the
+// neighbours' slots in the other buffer (shifted by at most one element).
+//
+// Work decomposition: a block owns a strip of 64*NW columns and marches up a
+// chunk of rows, one column per lane.  The moments a row's stencils need
+// (c, T, p) sit in an LDS ring of four rows, filled one row ahead of the row
+// being collided; helper lanes add the halo column on each side.  Two ways of
+// feeding rows are provided:
+//   step_kernel      rows are loaded into registers one row ahead (PIPE 1)
+//                    or loaded twice, for the moments and again for the
+//                    collision (PIPE 0);
+//   step_kernel_lds  one extra wave per block streams rows straight into LDS
+//                    (buffer_load ... lds) up to three rows ahead of the
+//                    collision, so the depth of the prefetch costs no
+//                    registers.
+// Either way every distribution is read from HBM once per step (halo columns
+// and the two boundary rows of a chunk are re-read from cache).
+//
+// Two arithmetic forms share the templates:
+//   R = double, DEV = false: FP64 values as defined by the paper;
+//   R = float,  DEV = true : FP32 deviations f - w p0, g_{1..8},
+//     hbar_{1..8} - w rho cv Ts (and FP64 g_0, hbar_0 - w0 rho cv Ts);
+//     Delta p and Delta T come from them, and every equilibrium is written as
+//     a deviation (w Delta p + rho cs^2 G, rho cv (Delta T w + T G), with
+//     G = Gamma_i(u) - w_i), so no large value is formed and then subtracted.
+#pragma once
+
+#include "lattice.h"
+
+namespace lbe {
+
+constexpr int kNumS = 25;  // planes in the storage type; two FP64 planes follow
+
+// plane of distribution q (0..26 = f, g, hbar; not 9 or 18, the FP64 planes)
+__host__ __device__ constexpr int plane_of(int q) { return q < 9 ? q : (q < 18 ? q - 1 : q - 2); }
+
+// constants in the kernel's arithmetic type
+template <typename R>
+struct Consts {
+  R rho, inv_rho, rcv, tauf0, dtauf, tauT0, dtauT, wg, gam3, kcap, epsalpha;
+  R sigma0, sigmaT, TsmTref, Tref, bfx, bfy;
+  __device__ explicit Consts(const StepArgs &a)
+      : rho(R(a.rho)), inv_rho(R(1.0 / a.rho)), rcv(R(a.rcv)), tauf0(R(a.tauf0)),
+        dtauf(R(a.dtauf)), tauT0(R(a.tauT0)), dtauT(R(a.dtauT)), wg(R(a.omg_g)),
+        gam3(R(a.gam3)), kcap(R(a.kcap)), epsalpha(R(a.epsalpha)), sigma0(R(a.sigma0)),
+        sigmaT(R(a.sigmaT)), TsmTref(R(a.Ts - a.Tref)), Tref(R(a.Tref)),
+        bfx(R(a.rho * a.ax)), bfy(R(a.rho * a.ay)) {}
+};
+
+// One row of a lane's column: v[q] for the 25 storage planes (v[9], v[18]
+// unused) and the two FP64 rest populations.
+template <typename R>
+struct RowVals {
+  R v[27];
+  double g0, h0;
+};
+
+// Moments of a loaded site: c (FP64), T or Delta T (FP64), p or Delta p.
+template <typename R>
+__device__ __forceinline__ void site_moments(const RowVals<R> &r, double inv_rcv, double *c,
+                                             double *T, R *p) {
+  R cs = 0, hs = 0, f = 0;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    f += r.v[q];
+    if (q > 0) {
+      cs += r.v[9 + q];
+      hs += r.v[18 + q];
+    }
+  }
+  *c = r.g0 + double(cs);
+  *T = (r.h0 + double(hs)) * inv_rcv;
+  *p = f;
+}
+
+// The collision, diagnostics and field output of site (x, j).  cS/cC/cN,
+// tS.., pS.. point at the ring entries west of the site in rows j-1, j, j+1
+// (index 0 west, 1 centre, 2 east).
+template <typename S, typename R, bool DEV, int MODE>
+__device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &k, int j, int x,
+                                            const double *cS, const double *cC, const double *cN,
+                                            const R *tS, const R *tC, const R *tN, const R *pS,
+                                            const R *pC, const R *pN, const RowVals<R> &cur,
+                                            double *acc) {
+  const int nx = a.nx, ny = a.ny;
+  const size_t n = (size_t)nx * (size_t)ny;
+  const R third = R(1) / R(3);
+  // order parameter and its stencils in FP64
+  const double cd = cC[1];
+  double gcx_d, gcy_d, lap_d, mu_d;
+  {
+    const double e = cC[2], w = cC[0], nn = cN[1], s = cS[1];
+    const double ne = cN[2], nw = cN[0], sw = cS[0], se = cS[2];
+    gcx_d = (e - w) * (1.0 / 3.0) + (ne + se - nw - sw) * (1.0 / 12.0);
+    gcy_d = (nn - s) * (1.0 / 3.0) + (ne + nw - se - sw) * (1.0 / 12.0);
+    lap_d = (2.0 / 3.0) * ((e - cd) + (w - cd) + (nn - cd) + (s - cd)) +
+            (1.0 / 6.0) * ((ne - cd) + (nw - cd) + (se - cd) + (sw - cd));
+    mu_d = a.beta2 * cd * (cd - 1.0) * (2.0 * cd - 1.0) - a.eps2 * lap_d;
+  }
+  const R c = R(cd);
+  const R mu = R(mu_d);
+  const R gcx = R(gcx_d), gcy = R(gcy_d);
+  const R Tv = tC[1];   // T, or Delta T in the FP32 form
+  const R pv = pC[1];   // p, or Delta p
+  auto grad = [&](const R *Sr, const R *Cr, const R *Nr, R *gx, R *gy) {
+    *gx = (Cr[2] - Cr[0]) * third + (Nr[2] + Sr[2] - Nr[0] - Sr[0]) * R(1.0 / 12.0);
+    *gy = (Nr[1] - Sr[1]) * third + (Nr[2] + Nr[0] - Sr[2] - Sr[0]) * R(1.0 / 12.0);
+  };
+  R gTx, gTy, gpx, gpy;
+  grad(tS, tC, tN, &gTx, &gTy);
+  grad(pS, pC, pN, &gpx, &gpy);
+  R jx = 0, jy = 0;
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    if (kEx[q] != 0) jx += R(kEx[q]) * cur.v[q];
+    if (kEy[q] != 0) jy += R(kEy[q]) * cur.v[q];
+  }
+  // closures
+  const R Tm = DEV ? Tv + k.TsmTref : Tv - k.Tref;   // T - Tref
+  const R sigma = k.sigma0 - k.sigmaT * Tm;
+  const R gsx = -k.sigmaT * gTx, gsy = -k.sigmaT * gTy;
+  const R g2 = gcx * gcx + gcy * gcy;
+  const R gds = gcx * gsx + gcy * gsy;
+  const R ks = k.kcap * sigma * mu;
+  const R Fx = ks * gcx + k.epsalpha * (g2 * gsx - gds * gcx) + k.bfx;
+  const R Fy = ks * gcy + k.epsalpha * (g2 * gsy - gds * gcy) + k.bfy;
+  const R ux = R(3) * jx * k.inv_rho + R(0.5) * Fx * k.inv_rho;
+  const R uy = R(3) * jy * k.inv_rho + R(0.5) * Fy * k.inv_rho;
+
+  if (MODE & kDiag) {
+    const double Td = DEV ? double(Tv) + a.Ts : double(Tv);
+    const double yy = double(j) + 0.5, xx = double(x) + 0.5;
+    acc[0] += cd;
+    acc[1] += a.rcv * Td;
+    acc[2] += cd * yy;
+    acc[3] += cd * xx;
+    if (cd >= 0.5) {
+      acc[4] += cd;
+      acc[5] += cd * double(uy);
+    }
+    const double chk = cd + Td + double(pv) + double(ux) + double(uy);
+    if (!isfinite(chk)) acc[6] += 1.0;
+  }
+  if (MODE & kFields) {
+    const size_t s = (size_t)j * nx + x;
+    if (a.phi) a.phi[s] = 2.0 * cd - 1.0;
+    if (a.ux) a.ux[s] = double(ux);
+    if (a.uy) a.uy[s] = double(uy);
+    if (a.p) a.p[s] = DEV ? double(pv) + a.p0 : double(pv);
+    if (a.T) a.T[s] = DEV ? double(Tv) + a.Ts : double(Tv);
+  }
+  if (MODE & kStore) {
+    S *dst = static_cast<S *>(a.dst);
+    const double *dst_d = reinterpret_cast<const double *>(dst + kNumS * n);
+    const size_t pbytes = n * sizeof(S);
+    const R ch = c < R(0) ? R(0) : (c > R(1) ? R(1) : c);
+    const R wf = R(1) / (k.tauf0 + ch * k.dtauf);
+    const R wT = R(1) / (k.tauT0 + ch * k.dtauT);
+    const R wg = k.wg;
+    const R Fbx = Fx - gpx, Fby = Fy - gpy;
+    const R usq = ux * ux + uy * uy;
+    // temperature in FP64 for the rest population, in R for the others
+    double hs = 0.0;
+#pragma unroll
+    for (int q = 1; q < 9; ++q) hs += double(cur.v[18 + q]);
+    const double Td = (cur.h0 + hs) / a.rcv;          // T or Delta T, FP64
+    const double Tfull_d = DEV ? Td + a.Ts : Td;
+    const R Tfull = R(Tfull_d);
+    const R rcvT = k.rcv * Tfull;
+    const R gmu = k.gam3 * mu;
+    const R cf = R(1) - R(0.5) * wf, cgf = R(1) - R(0.5) * wg, chf = R(1) - R(0.5) * wT;
+    const R src_g = R(3) * c * k.inv_rho;     // c / (rho cs^2)
+    const R src_h = R(3) * k.inv_rho;         // 1 / (rho cs^2)
+    const bool walls = a.walls_y != 0;
+    const bool bot = walls && j == 0, top = walls && j == ny - 1;
+    R gsum = 0;                                // sum of g_1..8 = c - g_0
+#pragma unroll
+    for (int q = 1; q < 9; ++q) gsum += cur.v[9 + q];
+    const uint32_t s_own = (uint32_t)(j * nx + x);
+    auto st = [&](int q, uint32_t off, R val) {
+      buf_store_nt<S>(S(val), plane_rsrc(dst + (size_t)plane_of(q) * n, pbytes),
+                      off * (uint32_t)sizeof(S));
+    };
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const R w = wq<R>(i);
+      const R e = R(kEx[i]) * ux + R(kEy[i]) * uy;
+      const R G = w * (R(3) * e + R(4.5) * e * e - R(1.5) * usq);  // Gamma_i - w_i
+      const R gam = w + G;
+      const R cxu = R(kEx[i]) - ux, cyu = R(kEy[i]) - uy;
+      const R fe = Fx * cxu + Fy * cyu;
+      const R fbe = Fbx * cxu + Fby * cyu;
+      // f (Eqs. 6-7): f^eq = w p + rho cs^2 G
+      const R feq = w * pv + k.rho * third * G;
+      const R fo = cur.v[i] - wf * (cur.v[i] - feq) + cf * fe * gam;
+      // g (Eqs. 12-14): g^eq_0 = c - (1 - w0) 3 Gamma mu + c G_0,
+      //                 g^eq_i = w_i 3 Gamma mu + c G_i
+      const R gsrc = cgf * src_g * fbe * gam;
+      // hbar (Eqs. 22, 25): h^eq = rho cv T Gamma_i
+      const R heq_full = rcvT * gam;
+      const R hsrc = chf * src_h * fbe * heq_full;
+      if (i == 0) {
+        // rest populations in FP64 from FP32 increments:
+        // g^eq_0 - g_0 = sum_{q>0} g_q - (1 - w0) 3 Gamma mu + c G_0
+        const R d0 = gsum - (R(1) - w) * gmu + c * G;
+        const double gnew = cur.g0 + double(wg * d0 + gsrc);
+        // h_0 - h^eq_0 (both FP64-sized; their difference is small)
+        const double hdiff = DEV ? cur.h0 - a.rcv * (Td * double(w) + Tfull_d * double(G))
+                                 : cur.h0 - a.rcv * Tfull_d * double(gam);
+        const double hnew = cur.h0 + double(-wT * R(hdiff) + hsrc);
+        st(0, s_own, fo);
+        buf_store_nt<double>(gnew, plane_rsrc(dst_d, n * 8), s_own * 8u);
+        buf_store_nt<double>(hnew, plane_rsrc(dst_d + n, n * 8), s_own * 8u);
+        continue;
+      }
+      const R geq = w * gmu + c * G;
+      const R go = cur.v[9 + i] - wg * (cur.v[9 + i] - geq) + gsrc;
+      const R heq = DEV ? k.rcv * (Tv * w + Tfull * G) : heq_full;
+      const R ho = cur.v[18 + i] - wT * (cur.v[18 + i] - heq) + hsrc;
+      // push to x + xi_i
+      const bool out = (kEy[i] < 0 && bot) || (kEy[i] > 0 && top);
+      if (out) {
+        // reflected into the opposite direction at this site
+        const int o = kOpp[i];
+        const double *tw = kEy[i] < 0 ? a.twb : a.twt;
+        const R twv = DEV ? R(tw[x] - a.Ts) : R(tw[x]);
+        st(o, s_own, fo);
+        st(9 + o, s_own, go);
+        st(18 + o, s_own, R(2) * w * k.rcv * twv - ho);
+      } else {
+        int xd = x + kEx[i];
+        xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
+        int yd = j + kEy[i];
+        yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
+        const uint32_t s = (uint32_t)(yd * nx + xd);
+        st(i, s, fo);
+        st(9 + i, s, go);
+        st(18 + i, s, ho);
+      }
+    }
+  }
+}
+
+// deterministic block reduction of the per-lane diagnostic sums: fixed
+// butterfly within each wave, then the wave partials summed in order
+template <int NWAVES>
+__device__ __forceinline__ void block_partials(const double *acc, double (*red)[kNumPartials],
+                                               int lane, double *out) {
+  const int wave = lane >> 6, wl = lane & 63;
+#pragma unroll
+  for (int q = 0; q < kNumPartials; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (wl == 0) red[wave][q] = v;
+  }
+  __syncthreads();
+  if (lane < kNumPartials) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVES; ++w) s += red[w][lane];
+    out[lane] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Register-fed variant.
+template <typename S, typename R, bool DEV, int MODE, int NW, int PIPE>
+__global__ void __launch_bounds__(64 * NW)
+step_kernel(const StepArgs a) {
+  constexpr int BX = 64 * NW;
+  __shared__ double ringc[4][BX + 2];     // c
+  __shared__ R ringt[4][BX + 2];          // T (or Delta T)
+  __shared__ R ringp[4][BX + 2];          // p (or Delta p)
+  __shared__ double red[NW][kNumPartials];
+
+  const int nx = a.nx, ny = a.ny;
+  const bool walls = a.walls_y != 0;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int strip = t % a.nstrips;
+  const int chunk = t / a.nstrips;
+  const int x0 = strip * BX;
+  const int nact = min(BX, nx - x0);
+  const int lane = threadIdx.x;
+  const bool act = lane < nact;
+  const int x = x0 + lane;
+  const int y0 = chunk * a.rows_per_chunk;
+  const int y1 = min(y0 + a.rows_per_chunk, ny);
+  const size_t n = (size_t)nx * (size_t)ny;
+  const S *__restrict__ src = static_cast<const S *>(a.src);
+  const double *__restrict__ src_d = reinterpret_cast<const double *>(src + kNumS * n);
+  const Consts<R> k(a);
+  const double inv_rcv = 1.0 / a.rcv;
+
+  // helper lanes (last wave): 0..2 sum the left halo column's c, T, p;
+  // 3..5 the right one's
+  const int hl = lane - (BX - 64);
+  const bool halo = hl >= 0 && hl < 6;
+  const int hside = hl / 3;
+  const int hfield = hl - 3 * hside;  // 0: c, 1: T, 2: p
+  const int hx = hside == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + nact == nx ? 0 : x0 + nact);
+  const int hpos = hside == 0 ? 0 : nact + 1;
+
+  const size_t pbytes = n * sizeof(S);
+  auto ld = [&](int q, uint32_t off) {
+    return R(buf_load<S>(plane_rsrc(src + (size_t)plane_of(q) * n, pbytes),
+                         off * (uint32_t)sizeof(S)));
+  };
+  auto ldd = [&](int which, uint32_t off) {
+    return buf_load<double>(plane_rsrc(src_d + (size_t)which * n, n * 8), off * 8u);
+  };
+  auto wrap_row = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
+  auto is_ghost = [&](int row) { return walls && (row < 0 || row >= ny); };
+
+  auto load_row = [&](int row, RowVals<R> &r) {
+    if (act) {
+      const uint32_t s = (uint32_t)(row * nx + x);
+#pragma unroll
+      for (int q = 0; q < 27; ++q)
+        if (q != 9 && q != 18) r.v[q] = ld(q, s);
+      r.g0 = ldd(0, s);
+      r.h0 = ldd(1, s);
+    }
+  };
+  auto put_moments = [&](int slot, int row, const RowVals<R> &r) {
+    if (act) {
+      double c, T;
+      R p;
+      site_moments(r, inv_rcv, &c, &T, &p);
+      ringc[slot][lane + 1] = c;
+      ringt[slot][lane + 1] = R(T);
+      ringp[slot][lane + 1] = p;
+    }
+    if (halo) {
+      const uint32_t s = (uint32_t)(row * nx + hx);
+      if (hfield == 0) {
+        R cs = 0;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) cs += ld(9 + q, s);
+        ringc[slot][hpos] = ldd(0, s) + double(cs);
+      } else if (hfield == 1) {
+        R hs = 0;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) hs += ld(18 + q, s);
+        ringt[slot][hpos] = R((ldd(1, s) + double(hs)) * inv_rcv);
+      } else {
+        R f = 0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f += ld(q, s);
+        ringp[slot][hpos] = f;
+      }
+    }
+  };
+  // ghost row beyond a wall from the adjacent row's slot: c and p mirrored,
+  // T_ghost = 2 T_wall - T (in deviations 2 (T_wall - Ts) - Delta T); each
+  // lane reads only entries it wrote itself
+  auto put_ghost = [&](int slot, int from, const double *tw) {
+    if (act) {
+      ringc[slot][lane + 1] = ringc[from][lane + 1];
+      ringp[slot][lane + 1] = ringp[from][lane + 1];
+      const R twv = DEV ? R(tw[x] - a.Ts) : R(tw[x]);
+      ringt[slot][lane + 1] = R(2) * twv - ringt[from][lane + 1];
+    }
+    if (halo) {
+      if (hfield == 0) {
+        ringc[slot][hpos] = ringc[from][hpos];
+      } else if (hfield == 1) {
+        const R twv = DEV ? R(tw[hx] - a.Ts) : R(tw[hx]);
+        ringt[slot][hpos] = R(2) * twv - ringt[from][hpos];
+      } else {
+        ringp[slot][hpos] = ringp[from][hpos];
+      }
+    }
+  };
+  auto moments_or_ghost = [&](int row, int adj, RowVals<R> &tmp) {
+    if (is_ghost(row)) {
+      put_ghost(row & 3, adj & 3, row < 0 ? a.twb : a.twt);
+    } else {
+      load_row(wrap_row(row), tmp);
+      put_moments(row & 3, wrap_row(row), tmp);
+    }
+  };
+
+  double acc[kNumPartials];
+#pragma unroll
+  for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
+
+  RowVals<R> cur, nxt;
+#pragma unroll
+  for (int q = 0; q < 27; ++q) cur.v[q] = nxt.v[q] = R(0);
+  cur.g0 = cur.h0 = nxt.g0 = nxt.h0 = 0.0;
+  load_row(y0, cur);
+  put_moments(y0 & 3, y0, cur);
+  moments_or_ghost(y0 - 1, y0, nxt);
+  for (int j = y0; j < y1; ++j) {
+    // moments of row j + 1 (PIPE 1 keeps its values for the next collision)
+    moments_or_ghost(j + 1, j, nxt);
+    __syncthreads();
+    if (PIPE == 0) load_row(j, cur);   // second read of row j, from cache
+    if (act) {
+      const int l = lane;
+      site_update<S, R, DEV, MODE>(a, k, j, x, &ringc[(j - 1) & 3][l], &ringc[j & 3][l],
+                                   &ringc[(j + 1) & 3][l], &ringt[(j - 1) & 3][l],
+                                   &ringt[j & 3][l], &ringt[(j + 1) & 3][l],
+                                   &ringp[(j - 1) & 3][l], &ringp[j & 3][l],
+                                   &ringp[(j + 1) & 3][l], cur, acc);
+    }
+    if (PIPE == 1) cur = nxt;
+  }
+  if (MODE & kDiag)
+    block_partials<NW>(acc, red, lane, a.partials + (size_t)blockIdx.x * kNumPartials);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-fed variant: NW compute waves plus one loader wave per block.
+//
+// The loader streams each row straight into LDS with 16-byte buffer_load ...
+// lds operations (64 lanes x 16 B = 1 KiB each) and stays ahead: row r uses
+// slot r % 4; while row j collides, row j + 1 is resident (its moments are
+// in the ring), row j + 2 is landing and row j + 3 has just been issued.  The
+// loader issues loads only, so it can wait for the older row with a counted
+// vmcnt.  Compute waves read their own column from LDS and never load from
+// memory.
+//
+// One wave-row in LDS: 25 planes x 64 x sizeof(S), then g_0 and hbar_0 (64
+// doubles each), padded to whole KiB.  The halo (the column on each side of
+// the strip) follows the NW wave-rows as single dwords: 25 values per side,
+// then g_0 and hbar_0 of both sides.
+template <typename S>
+struct LdsGeom {
+  static constexpr int kPlaneBytes = 64 * (int)sizeof(S);
+  static constexpr int kRowBytes = kNumS * kPlaneBytes + 2 * 512;           // real bytes
+  static constexpr int kInstr = (kRowBytes + 1023) / 1024;                  // 16-B DMA per lane
+  static constexpr int kRowPad = kInstr * 1024;
+  static constexpr int kValDw = (int)(sizeof(S) / 4);                        // dwords per value
+  static constexpr int kHaloDw = 2 * kNumS * kValDw + 8;
+  static constexpr int kHaloInstr = (kHaloDw + 63) / 64;
+  static constexpr int kHaloPad = kHaloInstr * 64 * 4;                      // bytes
+};
+
+// Workgroup barrier for the LDS-fed kernel.  Every wave first waits for its
+// own LDS writes (ring entries); the loader has already waited, with a counted
+// vmcnt, for the rows the others read next.  Written out so that no implicit
+// wait for all outstanding loads is placed before it, which would drain the
+// loader's prefetch at every barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <typename S, typename R, bool DEV, int MODE, int NW>
+__global__ void __launch_bounds__(64 * (NW + 1))
+step_kernel_lds(const StepArgs a) {
+  using G = LdsGeom<S>;
+  constexpr int BX = 64 * NW;
+  constexpr int NBUF = 4;
+  constexpr int kSlot = NW * G::kRowPad + G::kHaloPad;
+  __shared__ __attribute__((aligned(16))) char vals[NBUF * kSlot];
+  __shared__ double ringc[4][BX + 2];
+  __shared__ R ringt[4][BX + 2];
+  __shared__ R ringp[4][BX + 2];
+  __shared__ double red[NW + 1][kNumPartials];
+
+  const int nx = a.nx, ny = a.ny;
+  const bool walls = a.walls_y != 0;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int strip = t % a.nstrips;
+  const int chunk = t / a.nstrips;
+  const int x0 = strip * BX;
+  const int nact = min(BX, nx - x0);
+  const int lane = threadIdx.x;
+  const int wave = lane >> 6, wl = lane & 63;
+  const bool loader = wave == NW;
+  const bool act = !loader && lane < nact;
+  const int x = x0 + lane;
+  const int y0 = chunk * a.rows_per_chunk;
+  const int y1 = min(y0 + a.rows_per_chunk, ny);
+  const size_t n = (size_t)nx * (size_t)ny;
+  const Consts<R> k(a);
+  const double inv_rcv = 1.0 / a.rcv;
+  const int hx0 = x0 == 0 ? nx - 1 : x0 - 1;
+  const int hx1 = x0 + nact == nx ? 0 : x0 + nact;
+
+  auto wrap_row = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
+  auto is_ghost = [&](int row) { return walls && (row < 0 || row >= ny); };
+  auto slot_of = [&](int row) { return vals + (row & (NBUF - 1)) * kSlot; };
+
+  // ---- loader: row `row` (unwrapped index, for the slot) of the strip and
+  // its halo columns; the whole state is one buffer resource (< 2^32 bytes)
+  const __amdgpu_buffer_rsrc_t rs = plane_rsrc(a.src, kNumS * n * sizeof(S) + 2 * n * 8);
+  const uint32_t dbase = (uint32_t)(kNumS * n * sizeof(S));   // first FP64 plane
+  auto issue_row = [&](int row) {
+    char *slot = slot_of(row);
+    const uint32_t rbase = (uint32_t)wrap_row(row) * (uint32_t)nx;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t col0 = rbase + (uint32_t)(x0 + 64 * w);   // site of the wave's lane 0
+#pragma unroll
+      for (int i = 0; i < G::kInstr; ++i) {
+        const int b = (i * 64 + wl) * 16;   // byte of this lane's chunk in the wave-row
+        uint32_t off;
+        if (b < kNumS * G::kPlaneBytes) {
+          const int pl = b / G::kPlaneBytes, bo = b % G::kPlaneBytes;
+          off = (uint32_t)(pl * n * sizeof(S)) + col0 * (uint32_t)sizeof(S) + (uint32_t)bo;
+        } else if (b < G::kRowBytes) {
+          const int db = b - kNumS * G::kPlaneBytes;
+          off = dbase + (uint32_t)((db / 512) * n * 8) + col0 * 8u + (uint32_t)(db % 512);
+        } else {
+          off = col0 * (uint32_t)sizeof(S);   // padding: any in-range bytes
+        }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void *)(slot + w * G::kRowPad + i * 1024), 16,
+            off, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < G::kHaloInstr; ++i) {
+      const int d = i * 64 + wl;
+      uint32_t off;
+      if (d < 2 * kNumS * G::kValDw) {
+        const int e = d / G::kValDw, half = d % G::kValDw;
+        const int side = e / kNumS, pl = e % kNumS;
+        const uint32_t col = rbase + (uint32_t)(side ? hx1 : hx0);
+        off = (uint32_t)(pl * n * sizeof(S)) + col * (uint32_t)sizeof(S) + half * 4u;
+      } else if (d < G::kHaloDw) {
+        const int dd = d - 2 * kNumS * G::kValDw;            // 0..7
+        const int which = dd / 4, side = (dd / 2) % 2, half = dd % 2;
+        const uint32_t col = rbase + (uint32_t)(side ? hx1 : hx0);
+        off = dbase + (uint32_t)(which * n * 8) + col * 8u + half * 4u;
+      } else {
+        off = 0;
+      }
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rs, (__attribute__((address_space(3))) void *)(slot + NW * G::kRowPad + i * 256), 4, off,
+          0, 0, 0);
+    }
+  };
+  constexpr int kRowOps = NW * G::kInstr + G::kHaloInstr;
+  static_assert(kRowOps <= 63, "vmcnt range");
+  // gfx9 s_waitcnt immediate: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8
+  constexpr int kWaitRow = (kRowOps & 0xF) | ((kRowOps >> 4) << 14) | (0x7 << 4) | (0xF << 8);
+  constexpr int kWaitAll = (0x7 << 4) | (0xF << 8);
+  auto needs_load = [&](int row) { return row >= y0 - 1 && row <= y1 && !is_ghost(row); };
+
+  // ---- compute waves
+  auto read_row = [&](int row, RowVals<R> &r) {
+    const char *base = slot_of(row) + wave * G::kRowPad;
+#pragma unroll
+    for (int q = 0; q < 27; ++q)
+      if (q != 9 && q != 18)
+        r.v[q] = R(reinterpret_cast<const S *>(base + plane_of(q) * G::kPlaneBytes)[wl]);
+    const double *d = reinterpret_cast<const double *>(base + kNumS * G::kPlaneBytes);
+    r.g0 = d[wl];
+    r.h0 = d[64 + wl];
+  };
+  // helper lanes 0..5 of wave 0: halo moments from the slot
+  const bool helper = wave == 0 && wl < 6;
+  const int hside = wl / 3, hfield = wl - 3 * (wl / 3);
+  const int hpos = hside == 0 ? 0 : nact + 1;
+  auto halo_value = [&](const char *slot, int q) -> R {
+    const S *h = reinterpret_cast<const S *>(slot + NW * G::kRowPad);
+    return R(h[hside * kNumS + plane_of(q)]);
+  };
+  auto halo_double = [&](const char *slot, int which) -> double {
+    const double *h = reinterpret_cast<const double *>(slot + NW * G::kRowPad +
+                                                       2 * kNumS * sizeof(S));
+    return h[which * 2 + hside];
+  };
+  auto put_moments = [&](int row) {
+    const int rs4 = row & 3;
+    if (act) {
+      RowVals<R> r;
+      read_row(row, r);
+      double c, T;
+      R p;
+      site_moments(r, inv_rcv, &c, &T, &p);
+      ringc[rs4][lane + 1] = c;
+      ringt[rs4][lane + 1] = R(T);
+      ringp[rs4][lane + 1] = p;
+    }
+    if (helper) {
+      const char *sl = slot_of(row);
+      if (hfield == 0) {
+        R cs = 0;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) cs += halo_value(sl, 9 + q);
+        ringc[rs4][hpos] = halo_double(sl, 0) + double(cs);
+      } else if (hfield == 1) {
+        R hs = 0;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) hs += halo_value(sl, 18 + q);
+        ringt[rs4][hpos] = R((halo_double(sl, 1) + double(hs)) * inv_rcv);
+      } else {
+        R f = 0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f += halo_value(sl, q);
+        ringp[rs4][hpos] = f;
+      }
+    }
+  };
+  auto put_ghost = [&](int row, int from) {
+    const int s4 = row & 3, f4 = from & 3;
+    const double *tw = row < 0 ? a.twb : a.twt;
+    if (act) {
+      ringc[s4][lane + 1] = ringc[f4][lane + 1];
+      ringp[s4][lane + 1] = ringp[f4][lane + 1];
+      const R twv = DEV ? R(tw[x] - a.Ts) : R(tw[x]);
+      ringt[s4][lane + 1] = R(2) * twv - ringt[f4][lane + 1];
+    }
+    if (helper) {
+      if (hfield == 0) {
+        ringc[s4][hpos] = ringc[f4][hpos];
+      } else if (hfield == 1) {
+        const int hxs = hside ? hx1 : hx0;
+        const R twv = DEV ? R(tw[hxs] - a.Ts) : R(tw[hxs]);
+        ringt[s4][hpos] = R(2) * twv - ringt[f4][hpos];
+      } else {
+        ringp[s4][hpos] = ringp[f4][hpos];
+      }
+    }
+  };
+  auto moments_or_ghost = [&](int row, int adj) {
+    if (is_ghost(row)) put_ghost(row, adj);
+    else put_moments(row);
+  };
+
+  double acc[kNumPartials];
+#pragma unroll
+  for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
+
+  // prologue: the loader issues rows y0 - 1 .. y0 + 2 and waits for all but
+  // the last one issued; compute waves then put rows y0 - 1 and y0 in the ring
+  if (loader) {
+    for (int r = y0 - 1; r <= y0 + 2; ++r)
+      if (needs_load(r)) issue_row(r);
+    if (needs_load(y0 + 2)) __builtin_amdgcn_s_waitcnt(kWaitRow);
+    else __builtin_amdgcn_s_waitcnt(kWaitAll);
+  }
+  lds_barrier();
+  if (!loader) {
+    put_moments(y0);
+    moments_or_ghost(y0 - 1, y0);
+  }
+  for (int j = y0; j < y1; ++j) {
+    // moments of row j + 1 (landed); then the ring holds rows j - 1 .. j + 1
+    if (!loader) moments_or_ghost(j + 1, j);
+    lds_barrier();
+    if (loader) {
+      // row j - 1's slot is free: issue row j + 3, then wait for row j + 2
+      if (needs_load(j + 3)) {
+        issue_row(j + 3);
+        __builtin_amdgcn_s_waitcnt(kWaitRow);
+      } else {
+        __builtin_amdgcn_s_waitcnt(kWaitAll);
+      }
+    } else if (act) {
+      RowVals<R> cur;
+      read_row(j, cur);
+      const int l = lane;
+      site_update<S, R, DEV, MODE>(a, k, j, x, &ringc[(j - 1) & 3][l], &ringc[j & 3][l],
+                                   &ringc[(j + 1) & 3][l], &ringt[(j - 1) & 3][l],
+                                   &ringt[j & 3][l], &ringt[(j + 1) & 3][l],
+                                   &ringp[(j - 1) & 3][l], &ringp[j & 3][l],
+                                   &ringp[(j + 1) & 3][l], cur, acc);
+    }
+    lds_barrier();
+  }
+  if (MODE & kDiag)
+    block_partials<NW + 1>(acc, red, lane, a.partials + (size_t)blockIdx.x * kNumPartials);
+}
+
+}  // namespace lbe

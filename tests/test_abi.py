@@ -1,0 +1,107 @@
+"""Host-side checks of liblbe_csf.so: it loads, exports every function the
+header declares, and rejects bad arguments before touching a device.
+No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbe_csf.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"LBE_CSF_API\s+[\w\s\*]*?\b(lbe_csf_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def binding():
+    from paper_1412_6238_amd import lbe_csf
+    return lbe_csf
+
+
+def test_every_declared_symbol_is_exported(binding):
+    names = _declared()
+    assert len(names) == 13, names
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(binding.EXPORTED) == names
+
+
+def test_struct_layouts_match_header(binding, tmp_path):
+    """ctypes mirrors of the two structs match the C compiler's layout."""
+    import subprocess
+    prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "lbe_csf.h"', "int main(void){"]
+    for cname, py in (("lbe_csf_params", binding.lbe_csf_params), ("lbe_csf_diag", binding.lbe_csf_diag)):
+        prog.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            prog.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    prog.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(prog))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for cname, py in (("lbe_csf_params", binding.lbe_csf_params), ("lbe_csf_diag", binding.lbe_csf_diag)):
+        assert got[(cname, "size")] == ctypes.sizeof(py)
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_workspace_size_and_validation(binding):
+    from paper_1412_6238_amd import workloads as wl
+    p = wl.make("planar_marangoni")["params"]
+    P64 = binding.make_params(p, "fp64")
+    P32 = binding.make_params(p, "fp32_dev")
+    n64, n32 = binding.workspace_bytes(P64), binding.workspace_bytes(P32)
+    n = p["nx"] * p["ny"]
+    # a state: 25 planes of the storage type plus FP64 g_0 and hbar_0
+    s64, s32 = 25 * n * 8 + 16 * n, 25 * n * 4 + 16 * n
+    assert n64 >= 2 * s64 and n32 >= 2 * s32
+    assert n64 - 2 * s64 == n32 - 2 * s32   # same bookkeeping regions
+    rec = binding.workspace_bytes(P32, 4000)
+    # sqrt(N) checkpoints (63) + one replayed segment (64) + 2 adjoint states
+    assert rec - n32 >= (63 + 64 + 2) * s32
+    for bad in (dict(nx=2), dict(tau_f=(0.5, 1.0)), dict(tau_T=(1.0, 0.4)), dict(tau_g=0.5),
+                dict(mobility=0.0), dict(width=-1.0), dict(beta=0.0), dict(rho=0.0),
+                dict(sigmaT=float("nan"))):
+        Pb = binding.make_params(dict(p, **bad), "fp64")
+        with pytest.raises(binding.LbeCsfError) as e:
+            binding.workspace_bytes(Pb)
+        assert e.value.status == binding.LBE_CSF_EINVAL
+    Pb = binding.make_params(p, 7)
+    with pytest.raises(binding.LbeCsfError):
+        binding.workspace_bytes(Pb)
+
+
+def test_create_rejects_before_device_work(binding):
+    """Argument errors are detected on the host: small workspace -> ENOMEM,
+    misaligned workspace / NULL inputs -> EINVAL (fake pointers are never
+    dereferenced on these paths)."""
+    from paper_1412_6238_amd import workloads as wl
+    p = wl.make("poiseuille")["params"]
+    P = binding.make_params(p, "fp64")
+    need = binding.workspace_bytes(P)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)
+    rc = binding.lbe_csf_create(ctypes.byref(P), fake, need - 1, 0, None, fake, fake, fake, fake,
+                                ctypes.byref(h))
+    assert rc == binding.LBE_CSF_ENOMEM and not h.value
+    assert b"workspace too small" in binding.lbe_csf_last_error(None)
+    rc = binding.lbe_csf_create(ctypes.byref(P), ctypes.c_void_p((1 << 20) + 8), need, 0, None,
+                                fake, fake, fake, fake, ctypes.byref(h))
+    assert rc == binding.LBE_CSF_EINVAL
+    rc = binding.lbe_csf_create(ctypes.byref(P), fake, need, 0, None, None, fake, fake, fake,
+                                ctypes.byref(h))
+    assert rc == binding.LBE_CSF_EINVAL
+    rc = binding.lbe_csf_create(ctypes.byref(P), fake, need, 0, None, fake, fake, None, None,
+                                ctypes.byref(h))
+    assert rc == binding.LBE_CSF_EINVAL       # walls need wall temperatures
+    for s in range(-5, 1):
+        assert binding.lbe_csf_strerror(s)

@@ -1,0 +1,340 @@
+"""GPU parity: the HIP step (through the C ABI) against the FP64 CPU oracle.
+
+FP64: every field and every distribution within 1e-12 relative L2 (and
+1e-11 of the field's maximum elementwise).  FP32 deviations: against the FP64
+path at the error the precision allows.  Cases cover several strips and
+chunks with ragged tails, walls and periodic y, random non-equilibrium states,
+the workloads at oracle-feasible sizes, and the full 4096 x 4096 workload on
+sampled windows.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1412_6238_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi", "ux", "uy", "p", "T")
+
+
+@pytest.fixture(scope="module")
+def lbe():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1412_6238_amd import lbe_csf
+    return lbe_csf
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _cmp(gpu, orc, tol=1e-12, what=""):
+    """Relative L2 error <= tol per field, and elementwise <= 10 tol of the
+    field's largest magnitude.  The velocity is compared as one vector field
+    (a component that is only round-off, like u_y of a parallel flow, has no
+    meaningful relative error of its own)."""
+    g, o = dict(gpu), dict(orc)
+    if "ux" in o:
+        g["u"] = np.stack([g.pop("ux"), g.pop("uy")])
+        o["u"] = np.stack([o.pop("ux"), o.pop("uy")])
+    for k in o:
+        gk, ok = np.asarray(g[k]), np.asarray(o[k])
+        scale = max(np.abs(ok).max(), 1e-300)
+        assert np.all(np.isfinite(gk)), (what, k)
+        assert _rel(gk, ok) <= tol, (what, k, _rel(gk, ok))
+        assert np.abs(gk - ok).max() <= 10 * tol * scale, (what, k, np.abs(gk - ok).max() / scale)
+
+
+def _fields_np(sim):
+    return {k: v.cpu().numpy() for k, v in sim.fields().items()}
+
+
+def _pair(lbe, oracle_mod, case, precision="fp64", state=None):
+    p = case["params"]
+    sim = lbe.Simulation(p, case["phi0"], case["T0"], case["Twall_bot"], case["Twall_top"],
+                         precision=precision)
+    orc = oracle_mod.Oracle(p, case["Twall_bot"], case["Twall_top"]).init(case["phi0"], case["T0"])
+    if state is not None:
+        sim.set_state(state)
+        orc.set_state(state)
+    return sim, orc
+
+
+GRIDS = [(8, 8, 1), (16, 12, 0), (37, 21, 1), (70, 9, 1), (130, 7, 0), (600, 5, 1), (2100, 4, 1),
+         (64, 64, 0)]
+
+
+@pytest.mark.parametrize("nx,ny,walls", GRIDS)
+def test_fp64_initial_state_and_steps(lbe, oracle_mod, nx, ny, walls):
+    case = wl.random_case(nx, ny, seed=nx * 131 + ny, walls_y=walls)
+    _say(f"case random {nx}x{ny} walls={walls} fp64 from init")
+    sim, orc = _pair(lbe, oracle_mod, case)
+    _cmp({"F": sim.get_state().cpu().numpy()}, {"F": orc.state()}, what="F0")
+    _cmp(_fields_np(sim), orc.fields(), what="fields0")
+    for n in (1, 2, 4):
+        sim.step(n)
+        orc.step(n)
+        _cmp({"F": sim.get_state().cpu().numpy()}, {"F": orc.state()}, what=f"F after +{n}")
+        _cmp(_fields_np(sim), orc.fields(), what=f"fields after +{n}")
+
+
+@pytest.mark.parametrize("nx,ny,walls", GRIDS[:6])
+def test_fp64_random_state(lbe, oracle_mod, nx, ny, walls):
+    """Arbitrary non-equilibrium states, loaded through set_state."""
+    case = wl.random_case(nx, ny, seed=7 + nx, walls_y=walls)
+    F = wl.random_state(nx, ny, seed=nx + 3 * ny)
+    _say(f"case random state {nx}x{ny} walls={walls} fp64")
+    sim, orc = _pair(lbe, oracle_mod, case, state=F)
+    sim.step(3)
+    orc.step(3)
+    _cmp({"F": sim.get_state().cpu().numpy()}, {"F": orc.state()}, what="F")
+    _cmp(_fields_np(sim), orc.fields(), what="fields")
+
+
+def test_fp64_diagnostics(lbe, oracle_mod):
+    case = wl.random_case(90, 40, seed=4, walls_y=1)
+    _say("case diagnostics 90x40")
+    sim, orc = _pair(lbe, oracle_mod, case)
+    sim.step(5)
+    orc.step(5)
+    d, e = sim.diagnostics(), orc.diag()
+    for k in ("mass", "energy", "sum_cy", "sum_cx", "mass_thr", "sum_cuy_thr", "centroid_y", "u_r"):
+        assert d[k] == pytest.approx(e[k], rel=1e-12, abs=1e-15), k
+    assert d["n_nonfinite"] == 0 and d["step"] == 5
+
+
+@pytest.mark.parametrize("name,nsteps,p0", [("poiseuille", 20000, 1 / 3),
+                                            ("planar_marangoni", 5000, 0.0),
+                                            ("droplet", 60, 0.0), ("adjoint_droplet", 1000, 0.0)])
+def test_fp64_workloads(lbe, oracle_mod, name, nsteps, p0):
+    """The workloads at oracle-feasible step counts.  Droplet and planar cases
+    run in the p0 = 0 gauge (an exact symmetry of the method): at p0 = 1/3 the
+    populations are ~1e4 times the velocity they encode and the FP64
+    round-off of u alone approaches 1e-12.  The planar case is weaker still:
+    its Marangoni flow (|u| ~ 1e-6) is the small residue of capillary terms of
+    size ~1e-1 that cancel in mu, so its velocity is compared against the
+    oracle's own round-off floor, measured by re-running the oracle from an
+    initial state perturbed at the 1e-16 level."""
+    w = wl.make(name, p0=p0)
+    _say(f"case workload {name} fp64 {nsteps} steps p0={p0:.3f}")
+    sim, orc = _pair(lbe, oracle_mod, w)
+    sim.step(nsteps)
+    orc.step(nsteps)
+    g, o = _fields_np(sim), orc.fields()
+    # pressure compared in the p0 = 1/3 gauge (the same physical state)
+    g["p"] = g["p"] + (1 / 3 - p0)
+    o["p"] = o["p"] + (1 / 3 - p0)
+    if name == "planar_marangoni":
+        rng = np.random.default_rng(0)
+        phi_b = w["phi0"] * (1 + 2e-16 * rng.choice([-1.0, 1.0], w["phi0"].shape))
+        ob = oracle_mod.Oracle(w["params"], w["Twall_bot"], w["Twall_top"]).init(phi_b, w["T0"])
+        ob.step(nsteps)
+        fb = ob.fields()
+        floor = _rel(np.stack([fb["ux"], fb["uy"]]), np.stack([o["ux"], o["uy"]]))
+        err = _rel(np.stack([g["ux"], g["uy"]]), np.stack([o["ux"], o["uy"]]))
+        _say(f"  u: GPU vs oracle {err:.2e}, oracle round-off floor {floor:.2e}")
+        assert err <= max(1e-12, 10 * floor)
+        for k in ("ux", "uy"):
+            g.pop(k), o.pop(k)
+    _cmp(g, o, what=name)
+
+
+@pytest.mark.parametrize("pipe", ["0", "1", "3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
+def test_row_pipelines_agree(lbe, oracle_mod, monkeypatch, pipe, precision):
+    """The three ways of feeding rows (two register pipelines and the LDS-fed
+    kernel with its loader wave) give the same state, bit for bit, and FP64
+    matches the oracle."""
+    case = wl.random_case(136, 40, seed=21, walls_y=1)
+    monkeypatch.setenv("LBE_CSF_PIPE", pipe)
+    monkeypatch.setenv("LBE_CSF_ROWS", "7")
+    _say(f"case pipeline {pipe} {precision} 136x40")
+    sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                         case["Twall_top"], precision=precision)
+    sim.step(5)
+    F = sim.get_state().cpu().numpy()
+    monkeypatch.setenv("LBE_CSF_PIPE", "1")
+    ref = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                         case["Twall_top"], precision=precision)
+    ref.step(5)
+    np.testing.assert_array_equal(F, ref.get_state().cpu().numpy())
+    if precision == "fp64":
+        orc = oracle_mod.Oracle(case["params"], case["Twall_bot"], case["Twall_top"])
+        orc.init(case["phi0"], case["T0"]).step(5)
+        _cmp({"F": F}, {"F": orc.state()}, what="F")
+
+
+def test_fp64_chunking_does_not_matter(lbe, oracle_mod, monkeypatch):
+    """Different strip widths and chunk heights give bitwise-identical states."""
+    case = wl.random_case(200, 60, seed=12, walls_y=1)
+    out = []
+    for nw, rows in (("1", "3"), ("2", "7"), ("4", "60"), ("1", "1")):
+        monkeypatch.setenv("LBE_CSF_NW", nw)
+        monkeypatch.setenv("LBE_CSF_ROWS", rows)
+        _say(f"case chunking nw={nw} rows={rows}")
+        sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                             case["Twall_top"])
+        sim.step(6)
+        out.append(sim.get_state().cpu().numpy())
+    for o in out[1:]:
+        np.testing.assert_array_equal(o, out[0])
+
+
+def test_determinism(lbe):
+    w = wl.make("adjoint_droplet")
+    res = []
+    for _ in range(2):
+        _say("case determinism adjoint_droplet fp32_dev 50 steps")
+        sim = lbe.Simulation(w["params"], w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"],
+                             precision="fp32_dev", diag_every=10)
+        sim.step(50)
+        res.append((sim.get_state().cpu().numpy(), sim.diag_history()))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    assert res[0][1] == res[1][1]
+    assert [r["step"] for r in res[0][1]] == [0, 10, 20, 30, 40]
+
+
+def test_nonfinite_is_reported(lbe):
+    case = wl.random_case(32, 16, seed=1)
+    phi0 = case["phi0"].copy()
+    phi0[5, 7] = np.nan
+    _say("case non-finite injection")
+    sim = lbe.Simulation(case["params"], phi0, case["T0"], case["Twall_bot"], case["Twall_top"],
+                         diag_every=1)
+    with pytest.raises(lbe.LbeCsfError) as e:
+        sim.step(3)
+    assert e.value.status == lbe.LBE_CSF_ENONFINITE
+    assert sim.diagnostics()["n_nonfinite"] > 0
+
+
+def test_backward_requires_record(lbe):
+    case = wl.random_case(16, 16, seed=2)
+    sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                         case["Twall_top"], record_steps=8)
+    sim.step(4)
+    with pytest.raises(lbe.LbeCsfError) as e:
+        sim.backward(np.zeros((16, 16)))
+    assert e.value.status == lbe.LBE_CSF_ENOTRECORDED
+
+
+# ---- FP32 deviation form --------------------------------------------------------
+@pytest.mark.parametrize("name,nsteps,tol", [("planar_marangoni", 50000, 1e-4),
+                                             ("poiseuille", 20000, 1e-4),
+                                             ("droplet", 2000, 1e-4)])
+def test_fp32_dev_vs_fp64(lbe, name, nsteps, tol):
+    """FP32 deviation storage against the FP64 path after the stated steps:
+    relative L2 on phi, u and T within tol; mass drift reported."""
+    w = wl.make(name)
+    _say(f"case fp32_dev vs fp64 {name} {nsteps}")
+    res = {}
+    for prec in ("fp64", "fp32_dev"):
+        sim = lbe.Simulation(w["params"], w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"],
+                             precision=prec)
+        m0 = sim.diagnostics()["mass"]
+        sim.step(nsteps)
+        res[prec] = (_fields_np(sim), sim.diagnostics()["mass"] / m0 - 1)
+    a, b = res["fp32_dev"][0], res["fp64"][0]
+    ua, ub = np.stack([a["ux"], a["uy"]]), np.stack([b["ux"], b["uy"]])
+    errs = {"phi": _rel(a["phi"], b["phi"]), "u": _rel(ua, ub), "T": _rel(a["T"], b["T"]),
+            "T-Tmin": _rel(a["T"] - b["T"].min(), b["T"] - b["T"].min())}
+    _say(f"  errors {errs}  mass drift fp64 {res['fp64'][1]:.2e} fp32 {res['fp32_dev'][1]:.2e}")
+    for k in ("phi", "u", "T"):
+        assert errs[k] <= tol, (k, errs[k])
+
+
+def test_plain_fp32_would_fail_where_deviations_pass(lbe):
+    """Ablation (storage only): rounding the FP64 state to plain FP32 values
+    (not deviations) once destroys the Marangoni velocity of the planar case,
+    while the deviation form keeps it; this is why deviations are stored."""
+    import torch
+    w = wl.make("planar_marangoni")
+    sim = lbe.Simulation(w["params"], w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"])
+    sim.step(5000)
+    F = sim.get_state()
+    ref = _fields_np(sim)
+    sim.set_state(F.float().double())
+    plain = _fields_np(sim)
+    dev = lbe.Simulation(w["params"], w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"],
+                         precision="fp32_dev")
+    dev.set_state(F)
+    devf = _fields_np(dev)
+    e_plain, e_dev = _rel(plain["ux"], ref["ux"]), _rel(devf["ux"], ref["ux"])
+    _say(f"  u_x error after one FP32 rounding: plain {e_plain:.2e}, deviations {e_dev:.2e}")
+    assert e_dev < 1e-5 < e_plain
+
+
+# ---- full size, sampled -------------------------------------------------------------
+def _windows(nx, ny, k, rng, n):
+    """n windows of (2m+8) x (2m+8) sites, m = 2 + 2k, some touching the walls
+    and some wrapping in x; the centre 8 x 8 is valid after k steps."""
+    m = 2 + 2 * k
+    size = 2 * m + 8
+    wins = [(nx - m - 4, 0, size, m + 8), (3, ny - (m + 8), size, m + 8)]   # walls, x wrap
+    while len(wins) < n:
+        x0 = int(rng.integers(0, nx))
+        y0 = int(rng.integers(0, ny - size))
+        wins.append((x0, y0, size, size))
+    return wins, m
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32_dev", 1e-5), ("fp64", 1e-12)])
+def test_full_size_sampled(lbe, oracle_mod, precision, tol):
+    """The 4096 x 4096 multi-droplet workload in the benchmark's launch
+    configuration: k steps on the GPU, the oracle on windows around sampled
+    sites (its dependence cone is 2 sites per step), fields compared on the
+    windows' valid centres."""
+    w = wl.make("multi_droplet")
+    p = w["params"]
+    nx, ny = p["nx"], p["ny"]
+    k = 3
+    _say(f"case full-size multi_droplet {precision} {k} steps")
+    sim = lbe.Simulation(p, w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"], precision=precision)
+    sim.step(k)
+    g = {kk: v.cpu().numpy() for kk, v in sim.fields().items()}
+    del sim
+    umax = np.hypot(g["ux"], g["uy"]).max()
+    trange = w["T0"].max() - w["T0"].min()
+    rng = np.random.default_rng(99)
+    wins, m = _windows(nx, ny, k, rng, 12)
+    # also windows centred on droplet interfaces (where the force acts)
+    phi = w["phi0"]
+    iy, ix = np.nonzero(np.abs(phi) < 0.5)
+    for t in rng.choice(len(iy), 6, replace=False):
+        y0 = int(min(max(iy[t] - m - 4, 0), ny - (2 * m + 8)))
+        wins.append((int((ix[t] - m - 4) % nx), y0, 2 * m + 8, 2 * m + 8))
+    checked = 0
+    for (x0, y0, wx, wy) in wins:
+        cols = np.arange(x0, x0 + wx) % nx
+        sub = lambda a: np.ascontiguousarray(a[y0:y0 + wy][:, cols])
+        o = oracle_mod.Oracle(p, w["Twall_bot"], w["Twall_top"], window=(x0, y0, wx, wy))
+        o.init(sub(w["phi0"]), sub(w["T0"]))
+        o.step(k)
+        of = o.fields()
+        jj, ii = np.meshgrid(np.arange(wy), np.arange(wx), indexing="ij")
+        dist_x = np.minimum(ii, wx - 1 - ii)
+        dist_bot = jj if y0 > 0 else np.full_like(jj, 10 ** 6)
+        dist_top = (wy - 1 - jj) if y0 + wy < ny else np.full_like(jj, 10 ** 6)
+        valid = np.minimum(np.minimum(dist_x, dist_bot), dist_top) >= 2 + 2 * k
+        assert valid.sum() >= 64
+        gw = {f: sub(g[f])[valid] for f in FIELDS}
+        ow = {f: of[f][valid] for f in FIELDS}
+        for f in FIELDS:
+            assert np.all(np.isfinite(ow[f]))
+        # u against the largest speed of the whole field, T against its range
+        du = np.hypot(gw["ux"] - ow["ux"], gw["uy"] - ow["uy"]).max()
+        assert du <= tol * umax, ("u", x0, y0, du / umax)
+        assert np.abs(gw["phi"] - ow["phi"]).max() <= tol, ("phi", x0, y0)
+        assert np.abs(gw["T"] - ow["T"]).max() <= tol * trange, ("T", x0, y0)
+        assert np.abs(gw["p"] - ow["p"]).max() <= tol * np.abs(ow["p"]).max(), ("p", x0, y0)
+        checked += int(valid.sum())
+    _say(f"  compared {checked} sites in {len(wins)} windows")

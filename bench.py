@@ -22,7 +22,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_SITE = {"fp32_dev": 216, "fp64": 432}   # 27 values read + 27 written
+# algorithmic bytes per site update: the 27 distributions read once and
+# written once; the FP32 form keeps 25 in FP32 and the two rest populations
+# (g_0, hbar_0) in FP64: 2 x (25 x 4 + 2 x 8) = 232; FP64: 2 x 27 x 8 = 432
+BYTES_PER_SITE = {"fp32_dev": 232, "fp64": 432}
 KERNEL_SOURCES = ("paper_1412_6238_amd/csrc/step_kernel.h", "paper_1412_6238_amd/csrc/lattice.h")
 
 
@@ -82,7 +85,21 @@ def main():
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of known size (for scaling HBM "
+                         "byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        nbytes = 1 << 31
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_copy": nbytes,
+                          "bytes_written_per_copy": nbytes, "copies": 10}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "slab decomposition is a design, not part of this build.", file=sys.stderr)

@@ -66,27 +66,33 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, s
                                            0x00020000);
 }
 
+// byte_off: per-lane offset (vector register); base: uniform offset (scalar
+// register), e.g. the start of a plane inside one descriptor for the state
 template <typename T>
-__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off,
+                                      uint32_t base = 0) {
   if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off,
+                                                                       (int)base, 0));
   } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off,
+                                                                       (int)base, 0));
   }
 }
 
-#ifndef LBE_STORE_POLICY
-#define LBE_STORE_POLICY 2
-#endif
-// cache policy 2: non-temporal (the state written in one step is read back
-// only after the whole grid has been swept)
+// Stores use the default cache policy: measured on MI355X, marking these
+// (shifted, partially overlapping) row stores non-temporal made the step
+// slower, because neighbouring waves' partial lines then reach HBM unmerged.
 template <typename T>
-__device__ __forceinline__ void buf_store_nt(T v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+__device__ __forceinline__ void buf_store_nt(T v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off,
+                                             uint32_t base = 0) {
   if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)byte_off, 0, LBE_STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)byte_off,
+                                          (int)base, 0);
   } else {
     using V2 = __attribute__((ext_vector_type(2))) uint32_t;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)byte_off, 0, LBE_STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)byte_off,
+                                          (int)base, 0);
   }
 }
 

@@ -52,7 +52,7 @@ Launch pick_launch(int nx, int ny, size_t state_bytes) {
   }
   // the LDS-fed kernel moves 16-byte chunks (x a multiple of 4 keeps them
   // aligned) through one buffer descriptor (state below 4 GiB)
-  if (L.pipe == 3 && (nx % 4 != 0 || state_bytes >= (size_t(1) << 32))) L.pipe = 1;
+  if (L.pipe == 3 && nx % 4 != 0) L.pipe = 1;
   L.nw = nx >= 2048 ? 4 : (nx >= 512 ? 2 : 1);
   if (L.pipe == 3) L.nw = 1;
   if (const char *e = std::getenv("LBE_CSF_NW")) {
@@ -61,7 +61,9 @@ Launch pick_launch(int nx, int ny, size_t state_bytes) {
   }
   const int bx = 64 * L.nw;
   L.nstrips = (nx + bx - 1) / bx;
-  long long want = (2048LL + L.nstrips - 1) / L.nstrips;  // chunks for >= 2048 blocks
+  // about two resident blocks per CU: enough waves to cover latency while
+  // each block marches a long chunk (fewer halo rows re-read per chunk)
+  long long want = (512LL + L.nstrips - 1) / L.nstrips;
   int rows = (int)std::max<long long>(4, (ny + want - 1) / want);
   if (const char *e = std::getenv("LBE_CSF_ROWS")) {
     const int v = std::atoi(e);
@@ -86,7 +88,11 @@ bool params_valid(const lbe_csf_params *p, std::string *why) {
   };
   if (!p) return bad("params is NULL");
   if (p->nx < 3 || p->ny < 3) return bad("nx and ny must be >= 3");
-  if ((long long)p->nx * p->ny * 27LL >= (1LL << 40)) return bad("grid too large");
+  // the kernels address a state through one buffer descriptor (32-bit byte
+  // offsets): 25 planes of the storage type plus two FP64 planes < 4 GiB
+  const double vb = p->precision == LBE_CSF_FP64 ? 8.0 : 4.0;
+  if ((double)p->nx * (double)p->ny * (25.0 * vb + 16.0) >= 4294967296.0)
+    return bad("grid too large: a state must stay below 4 GiB");
   if (p->walls_y != 0 && p->walls_y != 1) return bad("walls_y must be 0 or 1");
   if (p->precision != LBE_CSF_FP64 && p->precision != LBE_CSF_FP32_DEV)
     return bad("unknown precision");

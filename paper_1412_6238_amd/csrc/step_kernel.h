@@ -173,9 +173,11 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     if (a.T) a.T[s] = DEV ? double(Tv) + a.Ts : double(Tv);
   }
   if (MODE & kStore) {
-    S *dst = static_cast<S *>(a.dst);
-    const double *dst_d = reinterpret_cast<const double *>(dst + kNumS * n);
-    const size_t pbytes = n * sizeof(S);
+    // one descriptor for the whole destination state (below 4 GiB); planes
+    // are selected by a scalar offset
+    const __amdgpu_buffer_rsrc_t rd = plane_rsrc(a.dst, kNumS * n * sizeof(S) + 2 * n * 8);
+    const uint32_t pbytes = (uint32_t)(n * sizeof(S));
+    const uint32_t dbase = kNumS * pbytes;
     const R ch = c < R(0) ? R(0) : (c > R(1) ? R(1) : c);
     const R wf = R(1) / (k.tauf0 + ch * k.dtauf);
     const R wT = R(1) / (k.tauT0 + ch * k.dtauT);
@@ -201,8 +203,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     for (int q = 1; q < 9; ++q) gsum += cur.v[9 + q];
     const uint32_t s_own = (uint32_t)(j * nx + x);
     auto st = [&](int q, uint32_t off, R val) {
-      buf_store_nt<S>(S(val), plane_rsrc(dst + (size_t)plane_of(q) * n, pbytes),
-                      off * (uint32_t)sizeof(S));
+      buf_store_nt<S>(S(val), rd, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes);
     };
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -232,8 +233,8 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
                                  : cur.h0 - a.rcv * Tfull_d * double(gam);
         const double hnew = cur.h0 + double(-wT * R(hdiff) + hsrc);
         st(0, s_own, fo);
-        buf_store_nt<double>(gnew, plane_rsrc(dst_d, n * 8), s_own * 8u);
-        buf_store_nt<double>(hnew, plane_rsrc(dst_d + n, n * 8), s_own * 8u);
+        buf_store_nt<double>(gnew, rd, s_own * 8u, dbase);
+        buf_store_nt<double>(hnew, rd, s_own * 8u, dbase + (uint32_t)(n * 8));
         continue;
       }
       const R geq = w * gmu + c * G;
@@ -311,7 +312,6 @@ step_kernel(const StepArgs a) {
   const int y1 = min(y0 + a.rows_per_chunk, ny);
   const size_t n = (size_t)nx * (size_t)ny;
   const S *__restrict__ src = static_cast<const S *>(a.src);
-  const double *__restrict__ src_d = reinterpret_cast<const double *>(src + kNumS * n);
   const Consts<R> k(a);
   const double inv_rcv = 1.0 / a.rcv;
 
@@ -324,13 +324,15 @@ step_kernel(const StepArgs a) {
   const int hx = hside == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + nact == nx ? 0 : x0 + nact);
   const int hpos = hside == 0 ? 0 : nact + 1;
 
-  const size_t pbytes = n * sizeof(S);
+  // one descriptor for the whole source state (below 4 GiB); planes are
+  // selected by a scalar offset
+  const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(src, kNumS * n * sizeof(S) + 2 * n * 8);
+  const uint32_t pbytes = (uint32_t)(n * sizeof(S));
   auto ld = [&](int q, uint32_t off) {
-    return R(buf_load<S>(plane_rsrc(src + (size_t)plane_of(q) * n, pbytes),
-                         off * (uint32_t)sizeof(S)));
+    return R(buf_load<S>(rsrc, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes));
   };
   auto ldd = [&](int which, uint32_t off) {
-    return buf_load<double>(plane_rsrc(src_d + (size_t)which * n, n * 8), off * 8u);
+    return buf_load<double>(rsrc, off * 8u, kNumS * pbytes + (uint32_t)which * (uint32_t)(n * 8));
   };
   auto wrap_row = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
   auto is_ghost = [&](int row) { return walls && (row < 0 || row >= ny); };

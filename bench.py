@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -75,6 +77,50 @@ def cpu_baseline(w, seconds=15.0):
                       f"{t2 - t0:.1f} s"}
 
 
+def adjoint_bench(args, torch, lbe_csf, wl):
+    """Cost of the gradient on the 256 x 512 droplet run (4000 steps, FP32
+    deviations): wall time of lbe_csf_backward (segment replay + adjoint
+    sweep) over the wall time of the recorded forward run, both timed with
+    events on the handle's stream after one untimed repetition."""
+    w = wl.make("adjoint_droplet")
+    p = w["params"]
+    nx, ny = p["nx"], p["ny"]
+    N = w["nsteps"]
+    prec = args.precision
+    dev = torch.device("cuda:0")
+    y = torch.arange(ny, dtype=torch.float64, device=dev)[:, None] + 0.5
+    out = None
+    for rep in range(2):
+        sim = lbe_csf.Simulation(p, w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"],
+                                 precision=prec, record_steps=N)
+        st = sim.stream
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        torch.cuda.synchronize()
+        e[0].record(st)
+        sim.step(N, record=True)
+        e[1].record(st)
+        cN = 0.5 * (1.0 + sim.fields(("phi",))["phi"])
+        seed = ((y - (cN * y).sum() / cN.sum()) / cN.sum()).expand(ny, nx).contiguous()
+        torch.cuda.synchronize()
+        e[2].record(st)
+        g = sim.backward(seed, want_T0=True)   # synchronises at its end
+        e[3].record(st)
+        torch.cuda.synchronize()
+        t_f = e[0].elapsed_time(e[1])
+        t_b = e[2].elapsed_time(e[3])
+        dtb = g["Twall"][0].cpu().numpy() + wl.conduction_field_T(g["T0"].cpu().numpy(), ny)
+        out = {"metric": "adjoint cost (backward / recorded forward)", "value": round(t_b / t_f, 3),
+               "unit": "ratio", "higher_is_better": False, "n_gpus": 1,
+               "config": {"workload": f"adjoint_droplet {nx}x{ny}", "steps": N,
+                          "precision": prec, "checkpoint_spacing": int(np.ceil(np.sqrt(N)))},
+               "forward_ms": round(t_f, 3), "backward_ms": round(t_b, 3),
+               "forward_mlups": round(nx * ny * N / (t_f / 1e3) / 1e6, 1),
+               "dJ_dsigmaT": g["sigmaT"], "dJ_dTw_bot_norm": float(np.linalg.norm(dtb)),
+               "rep": rep}
+        del sim
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +131,9 @@ def main():
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the differentiated droplet run instead: a recorded forward "
+                         "run and lbe_csf_backward (replay + reverse sweep); prints one JSON line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of known size (for scaling HBM "
                          "byte counters) and exit")
@@ -108,6 +157,9 @@ def main():
     import torch
     from paper_1412_6238_amd import lbe_csf, workloads as wl
 
+    if args.adjoint:
+        adjoint_bench(args, torch, lbe_csf, wl)
+        return
     w = wl.make(args.workload)
     p = w["params"]
     nx, ny = p["nx"], p["ny"]

@@ -75,6 +75,32 @@ Launch pick_launch(int nx, int ny, size_t state_bytes) {
   return L;
 }
 
+// adjoint launch: strips of 64*nw - 2 output columns (adjoint.h)
+struct AdjLaunch {
+  int nw, nstrips, rows, nchunks, nblocks;
+};
+
+AdjLaunch pick_adj_launch(int nx, int ny, bool fp64) {
+  AdjLaunch L;
+  L.nw = fp64 ? (nx >= 200 ? 2 : 1) : (nx >= 1024 ? 4 : (nx >= 200 ? 2 : 1));
+  if (const char *e = std::getenv("LBE_CSF_ADJ_NW")) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4) L.nw = v;
+  }
+  const int wout = 64 * L.nw - 2;
+  L.nstrips = (nx + wout - 1) / wout;
+  long long want = (512LL + L.nstrips - 1) / L.nstrips;
+  int rows = (int)std::max<long long>(4, (ny + want - 1) / want);
+  if (const char *e = std::getenv("LBE_CSF_ADJ_ROWS")) {
+    const int v = std::atoi(e);
+    if (v >= 1) rows = v;
+  }
+  L.rows = std::min(rows, ny);
+  L.nchunks = (ny + L.rows - 1) / L.rows;
+  L.nblocks = L.nstrips * L.nchunks;
+  return L;
+}
+
 struct Layout {
   size_t state_bytes;
   size_t off_a, off_b, off_tw, off_part, off_ring, off_cnt, off_rec, off_adj, total;
@@ -129,7 +155,8 @@ Layout make_layout(const lbe_csf_params *p, int64_t record_steps) {
   L.off_cnt = o; o = align_up(o + 4 * sizeof(int64_t));
   L.off_rec = o; o = align_up(o + sizeof(DiagRecord));
   L.off_adj = o;
-  L.adj = adj_layout(p->nx, L.state_bytes, la.nblocks, record_steps);
+  const AdjLaunch al = pick_adj_launch(p->nx, p->ny, vb == 8);
+  L.adj = adj_layout(p->nx, L.state_bytes, 27 * n * vb, al.nblocks, record_steps);
   o = align_up(o + L.adj.total);
   L.total = o;
   return L;
@@ -143,6 +170,7 @@ struct lbe_csf {
   lbe_csf_params P;
   Layout L;
   Launch la;
+  AdjLaunch al;
   hipStream_t stream;
   char *ws;
   void *state[2];
@@ -282,8 +310,83 @@ int launch_reduce(lbe_csf *h, int64_t step, bool append) {
   return LBE_CSF_OK;
 }
 
-int run_backward(lbe_csf *h, const double *, double *, double *, double *, const double *) {
-  return fail(h, LBE_CSF_EINVAL, "adjoint not available in this build");
+template <typename R, bool DEV>
+void launch_adj(const AdjLaunch &al, const AdjArgs &aa, hipStream_t st) {
+  switch (al.nw) {
+    case 1: adj_step_kernel<R, DEV, 1><<<al.nblocks, 64, 0, st>>>(aa); break;
+    case 2: adj_step_kernel<R, DEV, 2><<<al.nblocks, 128, 0, st>>>(aa); break;
+    default: adj_step_kernel<R, DEV, 4><<<al.nblocks, 256, 0, st>>>(aa); break;
+  }
+}
+
+// Reverse sweep over the recorded run: for each segment, last first, replay
+// the forward steps from its checkpoint into the tape, then apply the adjoint
+// step to the tape states in reverse order.
+int run_backward(lbe_csf *h, const double *dJdc, double *dsT, double *dTw, double *dF0,
+                 double *dT0) {
+  const AdjLayout &A = h->L.adj;
+  char *base = h->ws + h->L.off_adj;
+  const int nx = h->P.nx, ny = h->P.ny;
+  const size_t n = (size_t)nx * ny;
+  const bool f64 = h->P.precision == LBE_CSF_FP64;
+  hipStream_t st = h->stream;
+  void *lam[2] = {base + A.off_lam, base + A.off_lam + A.lam_bytes};
+  double *part = reinterpret_cast<double *>(base + A.off_part);
+  double *tw = reinterpret_cast<double *>(base + A.off_tw);
+  double *outv = reinterpret_cast<double *>(base + A.off_out);
+  const int nb = h->al.nblocks;
+  adj_zero_kernel<<<(nb + 255) / 256, 256, 0, st>>>(part, (size_t)nb);
+  adj_zero_kernel<<<(2 * nx + 255) / 256, 256, 0, st>>>(tw, 2 * (size_t)nx);
+  const dim3 g27((unsigned)((n + 255) / 256), 27);
+  if (f64) adj_seed_kernel<double><<<g27, 256, 0, st>>>(static_cast<double *>(lam[0]), dJdc, n);
+  else adj_seed_kernel<float><<<g27, 256, 0, st>>>(static_cast<float *>(lam[0]), dJdc, n);
+  HIPCHK(h, hipGetLastError());
+  int cur = 0;
+  const int64_t N = h->rec_steps, K = h->rec_K;
+  const int64_t nseg = (N + K - 1) / K;
+  if (nseg > A.nchk || K > A.K) return fail(h, LBE_CSF_EINVAL, "record exceeds the workspace");
+  AdjArgs aa;
+  aa.s = h->base;
+  aa.s.nstrips = h->al.nstrips;
+  aa.s.rows_per_chunk = h->al.rows;
+  aa.part = part;
+  aa.dtw = tw;
+  for (int64_t k = nseg - 1; k >= 0; --k) {
+    const int64_t m = std::min(K, N - k * K);
+    auto state = [&](int64_t j) -> void * {
+      return j == 0 ? base + A.off_chk + (size_t)k * A.state_bytes
+                    : base + A.off_tape + (size_t)j * A.state_bytes;
+    };
+    for (int64_t j = 1; j < m; ++j) {
+      const int rc = launch_step(h, kStore, state(j - 1), state(j), nullptr, nullptr, nullptr,
+                                 nullptr, nullptr);
+      if (rc != LBE_CSF_OK) return rc;
+    }
+    for (int64_t j = m - 1; j >= 0; --j) {
+      aa.s.src = state(j);
+      aa.lam_in = lam[cur];
+      aa.lam_out = lam[1 - cur];
+      if (f64) launch_adj<double, false>(h->al, aa, st);
+      else launch_adj<float, true>(h->al, aa, st);
+      HIPCHK(h, hipGetLastError());
+      cur = 1 - cur;
+    }
+  }
+  const unsigned g1 = (unsigned)((n + 255) / 256);
+  if (dF0 || dT0) {
+    if (f64)
+      adj_finish_kernel<double><<<g1, 256, 0, st>>>(static_cast<const double *>(lam[cur]), dF0,
+                                                    dT0, n, h->base.rcv);
+    else
+      adj_finish_kernel<float><<<g1, 256, 0, st>>>(static_cast<const float *>(lam[cur]), dF0,
+                                                   dT0, n, h->base.rcv);
+  }
+  adj_sum_kernel<<<1, 256, 0, st>>>(part, nb, outv);
+  HIPCHK(h, hipGetLastError());
+  if (dTw) HIPCHK(h, hipMemcpyAsync(dTw, tw, 2 * (size_t)nx * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(dsT, outv, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  return LBE_CSF_OK;
 }
 
 void to_public(const DiagRecord &r, lbe_csf_diag *o) {
@@ -336,6 +439,7 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   h->P = *params;
   h->L = L;
   h->la = pick_launch(params->nx, params->ny, L.state_bytes);
+  h->al = pick_adj_launch(params->nx, params->ny, params->precision == LBE_CSF_FP64);
   h->stream = static_cast<hipStream_t>(stream);
   h->ws = static_cast<char *>(workspace);
   h->state[0] = h->ws + L.off_a;

@@ -230,3 +230,45 @@ class Simulation:
         _check(lbe_csf_backward(self.h, _ptr(seed), ctypes.byref(s), _ptr(tw), _ptr(f0),
                                 _ptr(t0)), self.h)
         return dict(sigmaT=s.value, Twall=tw, F0=f0, T0=t0)
+
+
+class LbeRun(torch.autograd.Function):
+    """phi_N of an N-step run as a differentiable function of sigmaT, the wall
+    temperatures and the initial temperature field.
+
+    Forward: one recorded run (sqrt(N)-spaced checkpoints) in the library.
+    Backward: lbe_csf_backward with the seed dJ/dc = 2 dJ/dphi (phi = 2c - 1).
+    ``apply(sigmaT, Twall_bot, Twall_top, T0, params, phi0, nsteps, precision)``;
+    sigmaT is a 0-d tensor, Twall_* are (nx,) tensors (None with periodic y),
+    T0 is (ny, nx).  The handle stays with the graph until backward has run.
+    """
+
+    @staticmethod
+    def forward(ctx, sigmaT, Twall_bot, Twall_top, T0, params, phi0, nsteps, precision):
+        p = dict(params)
+        p["sigmaT"] = float(sigmaT.detach().cpu())
+        nsteps = int(nsteps)
+        sim = Simulation(p, phi0, T0.detach(), None if Twall_bot is None else Twall_bot.detach(),
+                         None if Twall_top is None else Twall_top.detach(), precision=precision,
+                         record_steps=nsteps, device=T0.device if T0.is_cuda else "cuda:0")
+        sim.step(nsteps, record=True)
+        phi = sim.fields(("phi",))["phi"]
+        ctx.sim = sim
+        ctx.has_walls = Twall_bot is not None
+        ctx.sT_device = sigmaT.device
+        return phi
+
+    @staticmethod
+    def backward(ctx, dphi):
+        sim = ctx.sim
+        g = sim.backward(2.0 * dphi.detach().to(torch.float64), want_F0=False, want_T0=True)
+        ctx.sim = None
+        dsT = torch.tensor(g["sigmaT"], dtype=torch.float64, device=ctx.sT_device)
+        dtb = g["Twall"][0] if ctx.has_walls else None
+        dtt = g["Twall"][1] if ctx.has_walls else None
+        return dsT, dtb, dtt, g["T0"], None, None, None, None
+
+
+def run_phi(params, phi0, T0, Twall_bot, Twall_top, nsteps, sigmaT, precision="fp32_dev"):
+    """phi after nsteps steps, differentiable w.r.t. sigmaT, Twall_* and T0."""
+    return LbeRun.apply(sigmaT, Twall_bot, Twall_top, T0, params, phi0, nsteps, precision)

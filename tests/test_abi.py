@@ -67,7 +67,8 @@ def test_workspace_size_and_validation(binding):
     assert n64 - 2 * s64 == n32 - 2 * s32   # same bookkeeping regions
     rec = binding.workspace_bytes(P32, 4000)
     # sqrt(N) checkpoints (63) + one replayed segment (64) + 2 adjoint states
-    assert rec - n32 >= (63 + 64 + 2) * s32
+    # (27 planes of FP32 each)
+    assert rec - n32 >= (63 + 64) * s32 + 2 * 27 * n * 4
     for bad in (dict(nx=2), dict(tau_f=(0.5, 1.0)), dict(tau_T=(1.0, 0.4)), dict(tau_g=0.5),
                 dict(mobility=0.0), dict(width=-1.0), dict(beta=0.0), dict(rho=0.0),
                 dict(sigmaT=float("nan"))):

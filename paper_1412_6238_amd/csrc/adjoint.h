@@ -1,29 +1,32 @@
 // adjoint.h -- reverse-mode differentiation of the fused step: checkpoint
-// layout, the adjoint step kernel and its helpers.
+// layout, the adjoint step kernels and their helpers.
 //
 // One step is F_{n+1} = Stream(Collide(F_n)).  Collide at site x depends on
 // F_n(x) and, through the nine-point stencils, on the moments (c, T, p) of the
 // eight neighbours.  For a cotangent lambda_{n+1} of F_{n+1} the adjoint step
-// returns lambda_n = (dF_{n+1}/dF_n)^T lambda_{n+1} in two stages per row:
-//   A  lambda* = Stream^T lambda_{n+1}: a pull from x + xi_i; at a wall the
-//      reflected population of the same site, with the sign flip of the
-//      anti-bounce-back for hbar (whose wall term 2 w rho cv T_wall gives
-//      dJ/dT_wall).  Then the transpose of the site's collision (site_adjoint):
-//      the direct cotangent of the 27 populations of x, and the cotangents
-//      a(x) of its seven stencil values (grad c, lap c, grad T, grad p), plus
-//      the site's share of dJ/dsigmaT;
-//   B  the stencil transposes: the moments of site y collect a(x) from every x
-//      whose stencil reads y (in the wall rows the ghost row mirrors c and p
-//      and holds 2 T_wall - T, so T collects with a minus sign and T_wall
-//      twice), and the moment cotangents go to the populations they sum
-//      (p = sum f, c = sum g, rho cv T = sum hbar).
-// Stage A at the strip edges needs moments one column further out, so a block
-// of 64*NW lanes produces 64*NW - 2 output columns; stage A runs one row ahead
-// of stage B, and the direct cotangent of a row waits one row in registers.
+// returns lambda_n = (dF_{n+1}/dF_n)^T lambda_{n+1}.  The cotangent is kept
+// in two parts, lambda_q = D_q + M_{group(q)}: D holds 27 planes and M three
+// (the shares of p = sum f, c = sum g and rho cv T = sum hbar, which reach
+// every population of a group alike).  One adjoint step is two kernels, one
+// thread per site, no recomputation:
+//   adj_collide_kernel  lambda* = Stream^T lambda_{n+1}, a pull from x + xi_i
+//       (at a wall the reflected population of the same site, with the sign
+//       flip of the anti-bounce-back for hbar, whose wall term 2 w rho cv
+//       T_wall gives dJ/dT_wall); then the transpose of the site's collision
+//       (site_adjoint): D_n(x), the stencil cotangents A_n(x) (grad c, lap c,
+//       grad T, grad p) and the site's share of dJ/dsigmaT;
+//   adj_stencil_kernel  the stencil transposes: the moments of site y collect
+//       A_n(x) from every x whose stencil reads y (in the wall rows the ghost
+//       row mirrors c and p and holds 2 T_wall - T, so T collects with a minus
+//       sign and T_wall twice) into M_n(y).
+// The linearisation point (c, T, p, j of F_n) comes from a moment tape that
+// the replay writes; the populations themselves are read only when the
+// relaxation times vary with c.
 //
 // The run is differentiated by sqrt(N) checkpointing: the forward run saves
 // every K-th state (K = ceil(sqrt N)); the backward pass replays each segment
-// from its checkpoint into a tape of K states and sweeps it in reverse.
+// from its checkpoint, writing the moment tape (and, with c-dependent
+// relaxation times, keeping the states), and sweeps it in reverse.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,15 +38,19 @@
 
 namespace lbe {
 
+constexpr int kAdjTX = 64;   // adjoint tile: 64 columns x 4 rows, one site per thread
+constexpr int kAdjTY = 4;
+
 struct AdjLayout {
   int64_t record_steps;   // capacity N
   int64_t K;              // checkpoint spacing for N steps
   int64_t nchk;           // checkpoints ceil(N / K)
   size_t state_bytes;     // one state (aligned)
-  size_t lam_bytes;       // one adjoint state: 27 planes of the arithmetic type
+  size_t mom_bytes;       // one moment set: c (FP64), T, p, jx, jy
+  size_t plane_bytes;     // one plane of the arithmetic type
   size_t off_chk;         // nchk states
-  size_t off_tape;        // K states (a replayed segment)
-  size_t off_lam;         // two adjoint states
+  size_t off_tape;        // K states, then K moment sets
+  size_t off_lam;         // D x2 (27 planes), M x2 (3 planes), A (7 planes)
   size_t off_part;        // per-block FP64 partial sums of dJ/dsigmaT
   size_t off_tw;          // FP64 [2][nx] dJ/dTwall accumulators
   size_t off_out;         // FP64 scalar result
@@ -58,21 +65,26 @@ inline int64_t adj_segment_length(int64_t nsteps) {
   return K;
 }
 
-inline AdjLayout adj_layout(int nx, size_t state_bytes, size_t lam_bytes, int nblocks,
+inline int adj_tiles_x(int nx) { return (nx + kAdjTX - 1) / kAdjTX; }
+inline int adj_tiles_y(int ny) { return (ny + kAdjTY - 1) / kAdjTY; }
+
+inline AdjLayout adj_layout(int nx, int ny, size_t state_bytes, size_t value_bytes,
                             int64_t record_steps) {
   AdjLayout A{};
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
   A.record_steps = record_steps;
   if (record_steps <= 0) return A;
+  const size_t n = (size_t)nx * ny;
   A.state_bytes = al(state_bytes);
-  A.lam_bytes = al(lam_bytes);
+  A.mom_bytes = al(n * (8 + 4 * value_bytes));
+  A.plane_bytes = al(n * value_bytes);
   A.K = adj_segment_length(record_steps);
   A.nchk = (record_steps + A.K - 1) / A.K;
   size_t o = 0;
   A.off_chk = o; o += (size_t)A.nchk * A.state_bytes;
-  A.off_tape = o; o += (size_t)A.K * A.state_bytes;
-  A.off_lam = o; o += 2 * A.lam_bytes;
-  A.off_part = o; o += al((size_t)nblocks * sizeof(double));
+  A.off_tape = o; o += (size_t)A.K * (A.state_bytes + A.mom_bytes);
+  A.off_lam = o; o += (2 * 27 + 2 * 3 + 7) * A.plane_bytes;
+  A.off_part = o; o += al((size_t)adj_tiles_x(nx) * adj_tiles_y(ny) * sizeof(double));
   A.off_tw = o; o += al(2 * (size_t)nx * sizeof(double));
   A.off_out = o; o += 256;
   A.total = o;
@@ -87,41 +99,36 @@ inline int adj_save_checkpoint(char *adj_base, const AdjLayout &A, int64_t k,
 }
 
 struct AdjArgs {
-  StepArgs s;               // constants, geometry (s.nstrips, s.rows_per_chunk of
-                            // the adjoint launch) and F_n in s.src
-  const void *lam_in;       // lambda_{n+1}: 27 planes of R, q = 0..26
-  void *lam_out;            // lambda_n
-  double *part;             // [gridDim.x] dJ/dsigmaT partials, accumulated
-  double *dtw;              // [2][nx] dJ/dT_wall (bottom, top), accumulated
+  StepArgs s;          // constants; s.tape = moments of F_n, s.src = F_n (VARTAU)
+  const void *d_in;    // D_{n+1}: 27 planes of R
+  const void *m_in;    // M_{n+1}: 3 planes of R (f, g, hbar groups)
+  void *d_out;         // D_n
+  void *a;             // A_n: 7 planes of R (collide writes, stencil reads)
+  void *m_out;         // M_n
+  double *part;        // [tiles] dJ/dsigmaT partials, accumulated over steps
+  double *dtw;         // [2][nx] dJ/dT_wall (bottom, top), accumulated
+  int ntx;             // tiles along x
 };
 
 // ---- transpose of one site's collision -------------------------------------
-// Inputs: the site's populations, its c (FP64) and stencil values, and lam
-// (cotangents of the 27 post-collision values of the site).  Outputs: db, the
-// cotangents of the 27 populations through this site's collision (including
-// the paths through its own moments c, T, p, j); da, the cotangents of the
-// seven stencil values (gcx, gcy, lapc, gTx, gTy, gpx, gpy), which stage B
-// hands on to the neighbours' moments; and *dsT += dJ/dsigmaT.  The arithmetic
-// differentiated is site_update's.
-template <typename R, bool DEV>
+// Inputs: the site's moments (p, j, T or their deviations; c in FP64), its
+// stencil values, lam (cotangents of the 27 post-collision values of the site)
+// and, when the relaxation times vary with c (VARTAU), its populations.
+// Outputs: db, the cotangents of the 27 populations through this site's
+// collision (including the paths through its own moments c, T, p, j); da, the
+// cotangents of the seven stencil values (gcx, gcy, lapc, gTx, gTy, gpx, gpy),
+// which the stencil transpose hands on to the neighbours' moments; and
+// *dsT += dJ/dsigmaT.  The arithmetic differentiated is site_update's.  With
+// constant relaxation times the populations enter the collision only through
+// the moments, so the moments suffice.
+template <typename R, bool DEV, bool VARTAU>
 __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> &k,
-                                             const RowVals<R> &cur, double cd, R gcx, R gcy,
-                                             R lapc, R gTx, R gTy, R gpx, R gpy, const R *lam,
-                                             R *db, R *da, double *dsT) {
+                                             const RowVals<R> &cur, R p, R jx, R jy, double Td,
+                                             double cd, R gcx, R gcy, R lapc, R gTx, R gTy,
+                                             R gpx, R gpy, const R *lam, R *db, R *da,
+                                             double *dsT) {
   const R third = R(1) / R(3);
   const R c = R(cd);
-  // forward values
-  R p = 0, jx = 0, jy = 0;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    p += cur.v[q];
-    if (kEx[q] != 0) jx += R(kEx[q]) * cur.v[q];
-    if (kEy[q] != 0) jy += R(kEy[q]) * cur.v[q];
-  }
-  double hs = 0.0;
-#pragma unroll
-  for (int q = 1; q < 9; ++q) hs += double(cur.v[18 + q]);
-  const double Td = (cur.h0 + hs) / a.rcv;           // T, or Delta T
   const double Tfull_d = DEV ? Td + a.Ts : Td;
   const R Tv = R(Td), Tfull = R(Tfull_d);
   const R mu = R(a.beta2 * cd * (cd - 1.0) * (2.0 * cd - 1.0) - a.eps2 * double(lapc));
@@ -165,7 +172,7 @@ __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> 
     // f' = f - wf (f - feq) + cf fe gam,  feq = w p + rho/3 G
     const R feq = w * p + k.rho * third * G;
     db[i] = Lf * (R(1) - wf);
-    b_wf -= Lf * (cur.v[i] - feq);
+    if (VARTAU) b_wf -= Lf * (cur.v[i] - feq);
     const R b_feq = Lf * wf;
     b_cf += Lf * fe * gam;
     R b_fe = Lf * cf * gam;
@@ -183,17 +190,19 @@ __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> 
     b_gmu += b_geq * (i == 0 ? -(R(1) - w) : w);
     b_G += b_geq * c;
     // h' = h - wT (h - heq) + chf src_h fbe heq,  heq = rho cv T gam
-    R hd;   // h - heq
-    if (i == 0) {
-      hd = R(DEV ? cur.h0 - a.rcv * (Td * double(w) + Tfull_d * double(G))
-                 : cur.h0 - a.rcv * Tfull_d * double(gam));
-    } else {
-      const R heq = DEV ? k.rcv * (Tv * w + Tfull * G) : rcvT * gam;
-      hd = cur.v[18 + i] - heq;
+    if (VARTAU) {
+      R hd;   // h - heq
+      if (i == 0) {
+        hd = R(DEV ? cur.h0 - a.rcv * (Td * double(w) + Tfull_d * double(G))
+                   : cur.h0 - a.rcv * Tfull_d * double(gam));
+      } else {
+        const R heq = DEV ? k.rcv * (Tv * w + Tfull * G) : rcvT * gam;
+        hd = cur.v[18 + i] - heq;
+      }
+      b_wT -= Lh * hd;
     }
     const R heq_full = rcvT * gam;
     db[18 + i] = Lh * (R(1) - wT);
-    b_wT -= Lh * hd;
     const R b_heq = Lh * (wT + chf * src_h * fbe);
     b_chf += Lh * src_h * fbe * heq_full;
     b_fbe += Lh * chf * src_h * heq_full;
@@ -223,7 +232,7 @@ __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> 
   b_Fx += b_Fbx;
   b_Fy += b_Fby;
   const R b_gpx = -b_Fbx, b_gpy = -b_Fby;
-  if (inside) b_c -= b_wf * wf * wf * k.dtauf + b_wT * wT * wT * k.dtauT;
+  if (VARTAU && inside) b_c -= b_wf * wf * wf * k.dtauf + b_wT * wT * wT * k.dtauT;
   const R b_jx = b_ux * R(3) * k.inv_rho, b_jy = b_uy * R(3) * k.inv_rho;
   b_Fx += b_ux * R(0.5) * k.inv_rho;
   b_Fy += b_uy * R(0.5) * k.inv_rho;
@@ -257,280 +266,266 @@ __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> 
   da[6] = b_gpy;
 }
 
-// ---- the adjoint step ---------------------------------------------------------
-// Block: a strip of output columns [x0, x0 + nout); lane l runs stage A for
-// column x0 - 1 + l (l <= nout + 1) and, for 1 <= l <= nout, stage B and the
-// output of that column.  Moments span x0 - 2 .. x0 + nout + 1 (LDS position
-// = column - x0 + 2).  Rows y0 - 1 .. y1 get stage A (the outer two only for
-// their stencil cotangents), rows y0 .. y1 - 1 stage B.
-template <typename R, bool DEV, int NW>
-__global__ void __launch_bounds__(64 * NW)
-adj_step_kernel(const AdjArgs aa) {
-  constexpr int BX = 64 * NW;
-  constexpr int WOUT = BX - 2;
-  __shared__ double ringc[4][BX + 2];
-  __shared__ R ringt[4][BX + 2];
-  __shared__ R ringp[4][BX + 2];
-  __shared__ R ringa[4][7][BX];
-  __shared__ double red[NW];
+
+// ---- adjoint step, part 1: pull and collision transpose ----------------------
+template <typename R, bool DEV, bool VARTAU>
+__global__ void __launch_bounds__(kAdjTX * kAdjTY)
+adj_collide_kernel(const AdjArgs aa) {
+  constexpr int TW = kAdjTX + 2, TH = kAdjTY + 2;
+  __shared__ double lc[TH][TW];
+  __shared__ R lt[TH][TW];
+  __shared__ R lp[TH][TW];
+  __shared__ double red[kAdjTX * kAdjTY / 64];
 
   const StepArgs &a = aa.s;
   const int nx = a.nx, ny = a.ny;
   const bool walls = a.walls_y != 0;
+  const size_t n = (size_t)nx * (size_t)ny;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int strip = tile % a.nstrips;
-  const int chunk = tile / a.nstrips;
-  const int x0 = strip * WOUT;
-  const int nout = min(WOUT, nx - x0);
-  const int lane = threadIdx.x;
+  const int x0 = (tile % aa.ntx) * kAdjTX, y0 = (tile / aa.ntx) * kAdjTY;
+  const int tid = threadIdx.x;
+  const double *tape_c = static_cast<const double *>(a.tape);
+  const R *tape_r = reinterpret_cast<const R *>(tape_c + n);
   auto wrapx = [&](int v) {
     v %= nx;
     return v < 0 ? v + nx : v;
   };
-  const int xa = wrapx(x0 - 1 + lane);
-  const bool actA = lane <= nout + 1;
-  const bool outl = lane >= 1 && lane <= nout;
-  const int y0 = chunk * a.rows_per_chunk;
-  const int y1 = min(y0 + a.rows_per_chunk, ny);
-  const size_t n = (size_t)nx * (size_t)ny;
-  const Consts<R> k(a);
-  const double inv_rcv = 1.0 / a.rcv;
-  using S = R;   // the state is stored in the arithmetic type
-
-  const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(a.src, kNumS * n * sizeof(S) + 2 * n * 8);
-  const uint32_t pbytes = (uint32_t)(n * sizeof(S));
-  const uint32_t lbytes = (uint32_t)(n * sizeof(R));
-  const __amdgpu_buffer_rsrc_t rin = plane_rsrc(aa.lam_in, 27 * n * sizeof(R));
-  const __amdgpu_buffer_rsrc_t rout = plane_rsrc(aa.lam_out, 27 * n * sizeof(R));
-  auto wrap_row = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
-  auto is_ghost = [&](int row) { return walls && (row < 0 || row >= ny); };
-  auto load_vals = [&](int row, int col, RowVals<R> &r) {
-    const uint32_t s = (uint32_t)(row * nx + col);
-#pragma unroll
-    for (int q = 0; q < 27; ++q)
-      if (q != 9 && q != 18)
-        r.v[q] = buf_load<S>(rsrc, s * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes);
-    r.g0 = buf_load<double>(rsrc, s * 8u, kNumS * pbytes);
-    r.h0 = buf_load<double>(rsrc, s * 8u, kNumS * pbytes + (uint32_t)(n * 8));
-  };
-  auto lin = [&](int q, uint32_t s) {
-    return buf_load<R>(rin, s * (uint32_t)sizeof(R), (uint32_t)q * lbytes);
+  auto wrapy = [&](int v) {
+    v %= ny;
+    return v < 0 ? v + ny : v;
   };
 
-  // moments: lane l at LDS position l + 1; helpers (lanes 0, 1 of the last
-  // wave) the columns x0 - 2 (position 0) and x0 + nout + 1 (position nout + 3)
-  const int hl = lane - (BX - 64);
-  const bool helper = hl == 0 || hl == 1;
-  const int hcol = wrapx(hl == 0 ? x0 - 2 : x0 + nout + 1);
-  const int hpos = hl == 0 ? 0 : nout + 3;
-  auto put_one = [&](int slot, int rr, int col, int pos) {
-    RowVals<R> r;
-    load_vals(rr, col, r);
-    double c, T;
-    R p;
-    site_moments(r, inv_rcv, &c, &T, &p);
-    ringc[slot][pos] = c;
-    ringt[slot][pos] = R(T);
-    ringp[slot][pos] = p;
-  };
-  auto put_moments = [&](int row) {
-    const int rr = wrap_row(row);
-    if (actA) put_one(row & 3, rr, xa, lane + 1);
-    if (helper) put_one(row & 3, rr, hcol, hpos);
-  };
-  // ghost row (halfway wall): c and p of the adjacent row, T = 2 T_wall - T
-  auto put_ghost = [&](int row, int from) {
-    const int s4 = row & 3, f4 = from & 3;
-    const double *tw = row < 0 ? a.twb : a.twt;
-    auto one = [&](int pos, int col) {
-      ringc[s4][pos] = ringc[f4][pos];
-      ringp[s4][pos] = ringp[f4][pos];
+  // moments of the tile and its one-site halo; ghost rows beyond a wall
+  // mirror c and p and hold T_ghost = 2 T_wall - T (deviations: 2 (T_wall -
+  // Ts) - Delta T)
+  for (int e = tid; e < TH * TW; e += kAdjTX * kAdjTY) {
+    const int r = e / TW, q = e - r * TW;
+    const int row = y0 - 1 + r, col = wrapx(x0 - 1 + q);
+    if (walls && (row < 0 || row >= ny)) {
+      const size_t s = (size_t)(row < 0 ? 0 : ny - 1) * nx + col;
+      const double *tw = row < 0 ? a.twb : a.twt;
       const R twv = DEV ? R(tw[col] - a.Ts) : R(tw[col]);
-      ringt[s4][pos] = R(2) * twv - ringt[f4][pos];
-    };
-    if (actA) one(lane + 1, xa);
-    if (helper) one(hpos, hcol);
-  };
-
-  double dsT = 0.0;
-  R dnew[27], dold[27];
-#pragma unroll
-  for (int q = 0; q < 27; ++q) dnew[q] = dold[q] = R(0);
-
-  // stage A of row t
-  auto stageA = [&](int t) {
-    R *const aslot = &ringa[t & 3][0][lane];
-    if (is_ghost(t) || !actA) {
-#pragma unroll
-      for (int m = 0; m < 7; ++m) aslot[m * BX] = R(0);
-      return;
+      lc[r][q] = tape_c[s];
+      lp[r][q] = tape_r[n + s];
+      lt[r][q] = R(2) * twv - tape_r[s];
+    } else {
+      const size_t s = (size_t)wrapy(row) * nx + col;
+      lc[r][q] = tape_c[s];
+      lt[r][q] = tape_r[s];
+      lp[r][q] = tape_r[n + s];
     }
-    const bool own = outl && t >= y0 && t < y1;
-    const int row = wrap_row(t);
-    RowVals<R> cur;
-    load_vals(row, xa, cur);
+  }
+  __syncthreads();
+
+  const int lx = tid & (kAdjTX - 1), ly = tid / kAdjTX;
+  const int x = x0 + lx, y = y0 + ly;
+  double ds = 0.0;
+  if (x < nx && y < ny) {
+    const Consts<R> k(a);
+    const uint32_t s = (uint32_t)(y * nx + x);
+    const uint32_t pb = (uint32_t)(n * sizeof(R));
+    const __amdgpu_buffer_rsrc_t rd = plane_rsrc(aa.d_in, 27 * n * sizeof(R));
+    const __amdgpu_buffer_rsrc_t rm = plane_rsrc(aa.m_in, 3 * n * sizeof(R));
+    auto ldD = [&](int q, uint32_t site) {
+      return buf_load<R>(rd, site * (uint32_t)sizeof(R), (uint32_t)q * pb);
+    };
+    auto ldM = [&](int g, uint32_t site) {
+      return buf_load<R>(rm, site * (uint32_t)sizeof(R), (uint32_t)g * pb);
+    };
     // lambda* = Stream^T lambda_{n+1}
     R lam[27];
-    const bool bot = walls && row == 0, top = walls && row == ny - 1;
-    const uint32_t s_own = (uint32_t)(row * nx + xa);
+    const bool bot = walls && y == 0, top = walls && y == ny - 1;
     double tw_acc = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const bool out = (kEy[i] < 0 && bot) || (kEy[i] > 0 && top);
+      uint32_t src = s;
+      int dq = i;
       if (out) {
-        const int o = kOpp[i];
-        lam[i] = lin(o, s_own);
-        lam[9 + i] = lin(9 + o, s_own);
-        const R lh = lin(18 + o, s_own);
+        dq = kOpp[i];
+      } else if (i != 0) {
+        src = (uint32_t)(wrapy(y + kEy[i]) * nx + wrapx(x + kEx[i]));
+      }
+      lam[i] = ldD(dq, src) + ldM(0, src);
+      lam[9 + i] = ldD(9 + dq, src) + ldM(1, src);
+      const R lh = ldD(18 + dq, src) + ldM(2, src);
+      if (out) {
         lam[18 + i] = -lh;
         tw_acc += 2.0 * double(wq<R>(i)) * a.rcv * double(lh);
       } else {
-        const int xd = wrapx(xa + kEx[i]);
-        const int yd = wrap_row(row + kEy[i]);
-        const uint32_t s = (uint32_t)(yd * nx + xd);
-        lam[i] = lin(i, s);
-        lam[9 + i] = lin(9 + i, s);
-        lam[18 + i] = lin(18 + i, s);
+        lam[18 + i] = lh;
       }
     }
-    if (own && (bot || top)) aa.dtw[(bot ? 0 : nx) + xa] += tw_acc;
-    // stencils at (xa, t), as in the forward step
-    const int l = lane;
-    const double *cS = &ringc[(t - 1) & 3][l], *cC = &ringc[t & 3][l];
-    const double *cN = &ringc[(t + 1) & 3][l];
-    const R *tS = &ringt[(t - 1) & 3][l], *tC = &ringt[t & 3][l], *tN = &ringt[(t + 1) & 3][l];
-    const R *pS = &ringp[(t - 1) & 3][l], *pC = &ringp[t & 3][l], *pN = &ringp[(t + 1) & 3][l];
-    const double cd = cC[1];
+    if (bot || top) aa.dtw[(bot ? 0 : nx) + x] += tw_acc;
+    // linearisation point and stencils, as in the forward step
+    const int cx = lx + 1, cy = ly + 1;
+    const double cd = lc[cy][cx];
     double gcx_d, gcy_d, lap_d;
     {
-      const double e = cC[2], w = cC[0], nn = cN[1], s = cS[1];
-      const double ne = cN[2], nw = cN[0], sw = cS[0], se = cS[2];
+      const double e = lc[cy][cx + 1], w = lc[cy][cx - 1], nn = lc[cy + 1][cx],
+                   so = lc[cy - 1][cx];
+      const double ne = lc[cy + 1][cx + 1], nw = lc[cy + 1][cx - 1], sw = lc[cy - 1][cx - 1],
+                   se = lc[cy - 1][cx + 1];
       gcx_d = (e - w) * (1.0 / 3.0) + (ne + se - nw - sw) * (1.0 / 12.0);
-      gcy_d = (nn - s) * (1.0 / 3.0) + (ne + nw - se - sw) * (1.0 / 12.0);
-      lap_d = (2.0 / 3.0) * ((e - cd) + (w - cd) + (nn - cd) + (s - cd)) +
+      gcy_d = (nn - so) * (1.0 / 3.0) + (ne + nw - se - sw) * (1.0 / 12.0);
+      lap_d = (2.0 / 3.0) * ((e - cd) + (w - cd) + (nn - cd) + (so - cd)) +
               (1.0 / 6.0) * ((ne - cd) + (nw - cd) + (se - cd) + (sw - cd));
     }
     const R third = R(1) / R(3);
-    auto grad = [&](const R *Sr, const R *Cr, const R *Nr, R *gx, R *gy) {
-      *gx = (Cr[2] - Cr[0]) * third + (Nr[2] + Sr[2] - Nr[0] - Sr[0]) * R(1.0 / 12.0);
-      *gy = (Nr[1] - Sr[1]) * third + (Nr[2] + Nr[0] - Sr[2] - Sr[0]) * R(1.0 / 12.0);
+    auto grad = [&](R (*f)[TW], R *gx, R *gy) {
+      *gx = (f[cy][cx + 1] - f[cy][cx - 1]) * third +
+            (f[cy + 1][cx + 1] + f[cy - 1][cx + 1] - f[cy + 1][cx - 1] - f[cy - 1][cx - 1]) *
+                R(1.0 / 12.0);
+      *gy = (f[cy + 1][cx] - f[cy - 1][cx]) * third +
+            (f[cy + 1][cx + 1] + f[cy + 1][cx - 1] - f[cy - 1][cx + 1] - f[cy - 1][cx - 1]) *
+                R(1.0 / 12.0);
     };
     R gTx, gTy, gpx, gpy;
-    grad(tS, tC, tN, &gTx, &gTy);
-    grad(pS, pC, pN, &gpx, &gpy);
-    R da[7];
-    double ds = 0.0;
-    site_adjoint<R, DEV>(a, k, cur, cd, R(gcx_d), R(gcy_d), R(lap_d), gTx, gTy, gpx, gpy, lam,
-                         dnew, da, &ds);
+    grad(lt, &gTx, &gTy);
+    grad(lp, &gpx, &gpy);
+    RowVals<R> cur;
+    if (VARTAU) {
+      const __amdgpu_buffer_rsrc_t rs =
+          plane_rsrc(a.src, kNumS * n * sizeof(R) + 2 * n * 8);
 #pragma unroll
-    for (int m = 0; m < 7; ++m) aslot[m * BX] = da[m];
-    if (own) dsT += ds;
-  };
-
-  // stage B of row t (a real row of the chunk); dold holds its direct part
-  auto stageB = [&](int t) {
-    if (!outl) return;
-    const int l = lane;
-    R cb = 0, Tb = 0, pb = 0;
-    // x = y - xi_k reads y through direction k of its stencil
-#pragma unroll
-    for (int kk = 1; kk < 9; ++kk) {
-      const int xr = t - kEy[kk];
-      if (is_ghost(xr)) continue;
-      const R *ar = &ringa[xr & 3][0][l - kEx[kk]];
-      const R wk = wq<R>(kk);
-      const R gx = R(3) * wk * R(kEx[kk]), gy = R(3) * wk * R(kEy[kk]);
-      cb += gx * ar[0] + gy * ar[BX] + R(6) * wk * ar[2 * BX];
-      Tb += gx * ar[3 * BX] + gy * ar[4 * BX];
-      pb += gx * ar[5 * BX] + gy * ar[6 * BX];
+      for (int q = 0; q < 27; ++q)
+        if (q != 9 && q != 18)
+          cur.v[q] = buf_load<R>(rs, s * (uint32_t)sizeof(R), (uint32_t)plane_of(q) * pb);
+      cur.g0 = buf_load<double>(rs, s * 8u, kNumS * pb);
+      cur.h0 = buf_load<double>(rs, s * 8u, kNumS * pb + (uint32_t)(n * 8));
     }
-    cb -= R(10.0 / 3.0) * ringa[t & 3][2][l];   // centre weight of the Laplacian
-    // wall rows: x in the same row whose stencil direction k points into the
-    // ghost row reads the mirror image of x + xi_k, which is y
-    if (walls && (t == 0 || t == ny - 1)) {
-      const int dir = t == 0 ? -1 : 1;
-      double twb = 0.0;
+    R db[27], da[7];
+    site_adjoint<R, DEV, VARTAU>(a, k, cur, lp[cy][cx], tape_r[2 * n + s], tape_r[3 * n + s],
+                                 double(lt[cy][cx]), cd, R(gcx_d), R(gcy_d), R(lap_d), gTx,
+                                 gTy, gpx, gpy, lam, db, da, &ds);
+    const __amdgpu_buffer_rsrc_t wd = plane_rsrc(aa.d_out, 27 * n * sizeof(R));
+    const __amdgpu_buffer_rsrc_t wa = plane_rsrc(aa.a, 7 * n * sizeof(R));
 #pragma unroll
-      for (int kk = 1; kk < 9; ++kk) {
-        if (kEy[kk] != dir) continue;
-        const R *ar = &ringa[t & 3][0][l - kEx[kk]];
-        const R wk = wq<R>(kk);
-        const R gx = R(3) * wk * R(kEx[kk]), gy = R(3) * wk * R(kEy[kk]);
-        cb += gx * ar[0] + gy * ar[BX] + R(6) * wk * ar[2 * BX];
-        pb += gx * ar[5 * BX] + gy * ar[6 * BX];
-        const R tg = gx * ar[3 * BX] + gy * ar[4 * BX];
-        Tb -= tg;
-        twb += 2.0 * double(tg);
-      }
-      aa.dtw[(t == 0 ? 0 : nx) + xa] += twb;
-    }
-    const uint32_t s = (uint32_t)(t * nx + xa);
-    const R Tpop = Tb * R(inv_rcv);
+    for (int q = 0; q < 27; ++q) buf_store_nt<R>(db[q], wd, s * (uint32_t)sizeof(R), (uint32_t)q * pb);
 #pragma unroll
-    for (int q = 0; q < 27; ++q) {
-      const R add = q < 9 ? pb : (q < 18 ? cb : Tpop);
-      buf_store_nt<R>(dold[q] + add, rout, s * (uint32_t)sizeof(R), (uint32_t)q * lbytes);
-    }
-  };
-
-  // prologue: rows y0 - 2 and y0 - 1 (a ghost row after its real neighbour)
-  {
-    const int r2 = y0 - 2, r1 = y0 - 1;
-    if (!is_ghost(r1)) put_moments(r1);
-    if (!is_ghost(r2)) put_moments(r2);
-    else if (!is_ghost(r1)) put_ghost(r2, r1);
-  }
-  for (int t = y0 - 1; t <= y1; ++t) {
-    const int tn = t + 1;
-    if (!is_ghost(tn)) put_moments(tn);
-    else if (!is_ghost(t)) put_ghost(tn, t);
-    if (t == y0 - 1 && is_ghost(t) && !is_ghost(tn)) put_ghost(t, tn);
-    __syncthreads();
-    stageA(t);
-    __syncthreads();
-    if (t - 1 >= y0) stageB(t - 1);
-#pragma unroll
-    for (int q = 0; q < 27; ++q) dold[q] = dnew[q];
+    for (int m = 0; m < 7; ++m) buf_store_nt<R>(da[m], wa, s * (uint32_t)sizeof(R), (uint32_t)m * pb);
   }
   // dJ/dsigmaT: deterministic block sum, accumulated over the steps
   {
-    const int wave = lane >> 6, wl = lane & 63;
-    double v = dsT;
+    const int wave = tid >> 6;
+    double v = ds;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (wl == 0) red[wave] = v;
+    if ((tid & 63) == 0) red[wave] = v;
     __syncthreads();
-    if (lane == 0) {
+    if (tid == 0) {
       double sum = 0.0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) sum += red[w];
+      for (int w = 0; w < kAdjTX * kAdjTY / 64; ++w) sum += red[w];
       aa.part[blockIdx.x] += sum;
     }
   }
 }
 
-// lambda_N from the seed on c = sum_q g_q: the seed on each g_q.
+// ---- adjoint step, part 2: stencil transposes --------------------------------
+template <typename R>
+__global__ void __launch_bounds__(kAdjTX * kAdjTY)
+adj_stencil_kernel(const AdjArgs aa) {
+  constexpr int TW = kAdjTX + 2, TH = kAdjTY + 2;
+  __shared__ R la[7][TH][TW];
+
+  const StepArgs &a = aa.s;
+  const int nx = a.nx, ny = a.ny;
+  const bool walls = a.walls_y != 0;
+  const size_t n = (size_t)nx * (size_t)ny;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % aa.ntx) * kAdjTX, y0 = (tile / aa.ntx) * kAdjTY;
+  const int tid = threadIdx.x;
+  const uint32_t pb = (uint32_t)(n * sizeof(R));
+  const __amdgpu_buffer_rsrc_t ra = plane_rsrc(aa.a, 7 * n * sizeof(R));
+  auto wrapx = [&](int v) {
+    v %= nx;
+    return v < 0 ? v + nx : v;
+  };
+  auto wrapy = [&](int v) {
+    v %= ny;
+    return v < 0 ? v + ny : v;
+  };
+  auto ghost = [&](int row) { return walls && (row < 0 || row >= ny); };
+  for (int e = tid; e < TH * TW; e += kAdjTX * kAdjTY) {
+    const int r = e / TW, q = e - r * TW;
+    const int row = y0 - 1 + r;
+    if (ghost(row)) {
+#pragma unroll
+      for (int m = 0; m < 7; ++m) la[m][r][q] = R(0);   // no stencil at a ghost site
+    } else {
+      const uint32_t s = (uint32_t)(wrapy(row) * nx + wrapx(x0 - 1 + q));
+#pragma unroll
+      for (int m = 0; m < 7; ++m) la[m][r][q] = buf_load<R>(ra, s * (uint32_t)sizeof(R), (uint32_t)m * pb);
+    }
+  }
+  __syncthreads();
+  const int lx = tid & (kAdjTX - 1), ly = tid / kAdjTX;
+  const int x = x0 + lx, y = y0 + ly;
+  if (x >= nx || y >= ny) return;
+  const int cx = lx + 1, cy = ly + 1;
+  R cb = 0, Tb = 0, pbv = 0;
+  // site x = y - xi_k reads y through direction k of its stencil
+#pragma unroll
+  for (int kk = 1; kk < 9; ++kk) {
+    const int r = cy - kEy[kk], q = cx - kEx[kk];
+    const R wk = wq<R>(kk);
+    const R gx = R(3) * wk * R(kEx[kk]), gy = R(3) * wk * R(kEy[kk]);
+    cb += gx * la[0][r][q] + gy * la[1][r][q] + R(6) * wk * la[2][r][q];
+    Tb += gx * la[3][r][q] + gy * la[4][r][q];
+    pbv += gx * la[5][r][q] + gy * la[6][r][q];
+  }
+  cb -= R(10.0 / 3.0) * la[2][cy][cx];   // centre weight of the Laplacian
+  // wall rows: a site x of the same row whose stencil direction k points into
+  // the ghost row reads the mirror image of x + xi_k, which is y
+  if (walls && (y == 0 || y == ny - 1)) {
+    const int dir = y == 0 ? -1 : 1;
+    double twb = 0.0;
+#pragma unroll
+    for (int kk = 1; kk < 9; ++kk) {
+      if (kEy[kk] != dir) continue;
+      const int q = cx - kEx[kk];
+      const R wk = wq<R>(kk);
+      const R gx = R(3) * wk * R(kEx[kk]), gy = R(3) * wk * R(kEy[kk]);
+      cb += gx * la[0][cy][q] + gy * la[1][cy][q] + R(6) * wk * la[2][cy][q];
+      pbv += gx * la[5][cy][q] + gy * la[6][cy][q];
+      const R tg = gx * la[3][cy][q] + gy * la[4][cy][q];
+      Tb -= tg;
+      twb += 2.0 * double(tg);
+    }
+    aa.dtw[(y == 0 ? 0 : nx) + x] += twb;
+  }
+  const uint32_t s = (uint32_t)(y * nx + x);
+  const __amdgpu_buffer_rsrc_t wm = plane_rsrc(aa.m_out, 3 * n * sizeof(R));
+  buf_store_nt<R>(pbv, wm, s * (uint32_t)sizeof(R), 0u);
+  buf_store_nt<R>(cb, wm, s * (uint32_t)sizeof(R), pb);
+  buf_store_nt<R>(Tb * R(1.0 / a.rcv), wm, s * (uint32_t)sizeof(R), 2 * pb);
+}
+
+// lambda_N from the seed on c = sum_q g_q: D = the seed on each g_q, M = 0.
 template <typename R>
 __global__ void __launch_bounds__(256)
-adj_seed_kernel(R *__restrict__ lam, const double *__restrict__ dJdc, size_t n) {
+adj_seed_kernel(R *__restrict__ d, R *__restrict__ m, const double *__restrict__ dJdc,
+                size_t n) {
   const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (s >= n) return;
-  lam[q * n + s] = (q >= 9 && q < 18) ? R(dJdc[s]) : R(0);
+  d[q * n + s] = (q >= 9 && q < 18) ? R(dJdc[s]) : R(0);
+  if (q < 3) m[q * n + s] = R(0);
 }
 
-// lambda_0 -> FP64 outputs: dJ/dF_0 (optional) and dJ/dT_0 through the initial
-// equilibrium hbar_i = w_i rho cv T_0 (optional).
+// lambda_0 = D_0 + M_0 -> FP64 outputs: dJ/dF_0 (optional) and dJ/dT_0 through
+// the initial equilibrium hbar_i = w_i rho cv T_0 (optional).
 template <typename R>
 __global__ void __launch_bounds__(256)
-adj_finish_kernel(const R *__restrict__ lam, double *__restrict__ dF0, double *__restrict__ dT0,
-                  size_t n, double rcv) {
+adj_finish_kernel(const R *__restrict__ d, const R *__restrict__ m, double *__restrict__ dF0,
+                  double *__restrict__ dT0, size_t n, double rcv) {
   const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   double t = 0.0;
 #pragma unroll
   for (int q = 0; q < 27; ++q) {
-    const double v = double(lam[q * n + s]);
+    const double v = double(d[q * n + s]) + double(m[(q / 9) * n + s]);
     if (dF0) dF0[q * n + s] = v;
     if (q >= 18) t += wq<double>(q - 18) * rcv * v;
   }

@@ -25,7 +25,8 @@ __host__ __device__ constexpr R wq(int i) {
 enum : int {
   kStore = 1,   // collide and stream into dst
   kFields = 2,  // write phi, u, p, T
-  kDiag = 4     // per-block FP64 partial sums of the diagnostics
+  kDiag = 4,    // per-block FP64 partial sums of the diagnostics
+  kTape = 8     // write the moments of the source state to the tape
 };
 
 constexpr int kNumPartials = 7;  // mass, energy, cy, cx, mass_thr, cuy_thr, nonfinite
@@ -54,6 +55,10 @@ struct StepArgs {
   // outputs
   double *phi, *ux, *uy, *p, *T;
   double *partials;         // [gridDim.x][kNumPartials]
+  // moment tape of the source state (kTape; read by the adjoint): c as FP64,
+  // then T, p, jx, jy in the arithmetic type (T and p as deviations in the
+  // FP32 form), each a plane of nx*ny
+  void *tape;
 };
 
 // Buffer resources: one descriptor per plane (scalar registers) and a 32-bit

@@ -53,7 +53,7 @@ Launch pick_launch(int nx, int ny, size_t state_bytes) {
   // the LDS-fed kernel moves 16-byte chunks (x a multiple of 4 keeps them
   // aligned) through one buffer descriptor (state below 4 GiB)
   if (L.pipe == 3 && nx % 4 != 0) L.pipe = 1;
-  L.nw = nx >= 2048 ? 4 : (nx >= 512 ? 2 : 1);
+  L.nw = nx >= 2048 ? 4 : (nx >= 256 ? 2 : 1);
   if (L.pipe == 3) L.nw = 1;
   if (const char *e = std::getenv("LBE_CSF_NW")) {
     const int v = std::atoi(e);
@@ -61,37 +61,12 @@ Launch pick_launch(int nx, int ny, size_t state_bytes) {
   }
   const int bx = 64 * L.nw;
   L.nstrips = (nx + bx - 1) / bx;
-  // about two resident blocks per CU: enough waves to cover latency while
-  // each block marches a long chunk (fewer halo rows re-read per chunk)
-  long long want = (512LL + L.nstrips - 1) / L.nstrips;
-  int rows = (int)std::max<long long>(4, (ny + want - 1) / want);
+  // about 2048 waves (two per SIMD) in one wave of resident blocks: long
+  // chunks on large grids (fewer halo rows re-read per chunk), down to one
+  // row per block on small grids, where the parallelism is the limit
+  const long long want = std::max(1LL, 2048LL / ((long long)L.nw * L.nstrips));
+  int rows = (int)std::max<long long>(1, (ny + want - 1) / want);
   if (const char *e = std::getenv("LBE_CSF_ROWS")) {
-    const int v = std::atoi(e);
-    if (v >= 1) rows = v;
-  }
-  L.rows = std::min(rows, ny);
-  L.nchunks = (ny + L.rows - 1) / L.rows;
-  L.nblocks = L.nstrips * L.nchunks;
-  return L;
-}
-
-// adjoint launch: strips of 64*nw - 2 output columns (adjoint.h)
-struct AdjLaunch {
-  int nw, nstrips, rows, nchunks, nblocks;
-};
-
-AdjLaunch pick_adj_launch(int nx, int ny, bool fp64) {
-  AdjLaunch L;
-  L.nw = fp64 ? (nx >= 200 ? 2 : 1) : (nx >= 1024 ? 4 : (nx >= 200 ? 2 : 1));
-  if (const char *e = std::getenv("LBE_CSF_ADJ_NW")) {
-    const int v = std::atoi(e);
-    if (v == 1 || v == 2 || v == 4) L.nw = v;
-  }
-  const int wout = 64 * L.nw - 2;
-  L.nstrips = (nx + wout - 1) / wout;
-  long long want = (512LL + L.nstrips - 1) / L.nstrips;
-  int rows = (int)std::max<long long>(4, (ny + want - 1) / want);
-  if (const char *e = std::getenv("LBE_CSF_ADJ_ROWS")) {
     const int v = std::atoi(e);
     if (v >= 1) rows = v;
   }
@@ -155,8 +130,7 @@ Layout make_layout(const lbe_csf_params *p, int64_t record_steps) {
   L.off_cnt = o; o = align_up(o + 4 * sizeof(int64_t));
   L.off_rec = o; o = align_up(o + sizeof(DiagRecord));
   L.off_adj = o;
-  const AdjLaunch al = pick_adj_launch(p->nx, p->ny, vb == 8);
-  L.adj = adj_layout(p->nx, L.state_bytes, 27 * n * vb, al.nblocks, record_steps);
+  L.adj = adj_layout(p->nx, p->ny, L.state_bytes, vb, record_steps);
   o = align_up(o + L.adj.total);
   L.total = o;
   return L;
@@ -170,7 +144,6 @@ struct lbe_csf {
   lbe_csf_params P;
   Layout L;
   Launch la;
-  AdjLaunch al;
   hipStream_t stream;
   char *ws;
   void *state[2];
@@ -277,15 +250,18 @@ void launch_prec(int mode, const Launch &la, const StepArgs &a, hipStream_t st) 
     case kStore | kDiag: launch_mode<S, R, DEV, kStore | kDiag>(la, a, st); break;
     case kFields: launch_mode<S, R, DEV, kFields>(la, a, st); break;
     case kDiag: launch_mode<S, R, DEV, kDiag>(la, a, st); break;
+    case kStore | kTape: launch_mode<S, R, DEV, kStore | kTape>(la, a, st); break;
+    case kTape: launch_mode<S, R, DEV, kTape>(la, a, st); break;
     default: launch_mode<S, R, DEV, kFields | kDiag>(la, a, st); break;
   }
 }
 
 int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
-                double *ux, double *uy, double *p, double *T) {
+                double *ux, double *uy, double *p, double *T, void *tape = nullptr) {
   StepArgs a = h->base;
   a.src = src;
   a.dst = dst;
+  a.tape = tape;
   a.phi = phi;
   a.ux = ux;
   a.uy = uy;
@@ -310,18 +286,18 @@ int launch_reduce(lbe_csf *h, int64_t step, bool append) {
   return LBE_CSF_OK;
 }
 
+// One adjoint step: collision transpose, then stencil transpose.
 template <typename R, bool DEV>
-void launch_adj(const AdjLaunch &al, const AdjArgs &aa, hipStream_t st) {
-  switch (al.nw) {
-    case 1: adj_step_kernel<R, DEV, 1><<<al.nblocks, 64, 0, st>>>(aa); break;
-    case 2: adj_step_kernel<R, DEV, 2><<<al.nblocks, 128, 0, st>>>(aa); break;
-    default: adj_step_kernel<R, DEV, 4><<<al.nblocks, 256, 0, st>>>(aa); break;
-  }
+void launch_adj(bool vartau, const AdjArgs &aa, int nblocks, hipStream_t st) {
+  if (vartau) adj_collide_kernel<R, DEV, true><<<nblocks, kAdjTX * kAdjTY, 0, st>>>(aa);
+  else adj_collide_kernel<R, DEV, false><<<nblocks, kAdjTX * kAdjTY, 0, st>>>(aa);
+  adj_stencil_kernel<R><<<nblocks, kAdjTX * kAdjTY, 0, st>>>(aa);
 }
 
 // Reverse sweep over the recorded run: for each segment, last first, replay
-// the forward steps from its checkpoint into the tape, then apply the adjoint
-// step to the tape states in reverse order.
+// the forward steps from its checkpoint (writing the moment tape, and keeping
+// the states when the relaxation times vary with c), then apply the adjoint
+// step in reverse order.
 int run_backward(lbe_csf *h, const double *dJdc, double *dsT, double *dTw, double *dF0,
                  double *dT0) {
   const AdjLayout &A = h->L.adj;
@@ -330,44 +306,64 @@ int run_backward(lbe_csf *h, const double *dJdc, double *dsT, double *dTw, doubl
   const size_t n = (size_t)nx * ny;
   const bool f64 = h->P.precision == LBE_CSF_FP64;
   hipStream_t st = h->stream;
-  void *lam[2] = {base + A.off_lam, base + A.off_lam + A.lam_bytes};
+  char *lam = base + A.off_lam;
+  const size_t pl = A.plane_bytes;
+  void *D[2] = {lam, lam + 27 * pl};
+  void *M[2] = {lam + 54 * pl, lam + 57 * pl};
+  void *Abuf = lam + 60 * pl;
   double *part = reinterpret_cast<double *>(base + A.off_part);
   double *tw = reinterpret_cast<double *>(base + A.off_tw);
   double *outv = reinterpret_cast<double *>(base + A.off_out);
-  const int nb = h->al.nblocks;
+  const int ntx = adj_tiles_x(nx), nb = ntx * adj_tiles_y(ny);
   adj_zero_kernel<<<(nb + 255) / 256, 256, 0, st>>>(part, (size_t)nb);
   adj_zero_kernel<<<(2 * nx + 255) / 256, 256, 0, st>>>(tw, 2 * (size_t)nx);
   const dim3 g27((unsigned)((n + 255) / 256), 27);
-  if (f64) adj_seed_kernel<double><<<g27, 256, 0, st>>>(static_cast<double *>(lam[0]), dJdc, n);
-  else adj_seed_kernel<float><<<g27, 256, 0, st>>>(static_cast<float *>(lam[0]), dJdc, n);
+  if (f64)
+    adj_seed_kernel<double><<<g27, 256, 0, st>>>(static_cast<double *>(D[0]),
+                                                 static_cast<double *>(M[0]), dJdc, n);
+  else
+    adj_seed_kernel<float><<<g27, 256, 0, st>>>(static_cast<float *>(D[0]),
+                                                static_cast<float *>(M[0]), dJdc, n);
   HIPCHK(h, hipGetLastError());
   int cur = 0;
   const int64_t N = h->rec_steps, K = h->rec_K;
   const int64_t nseg = (N + K - 1) / K;
   if (nseg > A.nchk || K > A.K) return fail(h, LBE_CSF_EINVAL, "record exceeds the workspace");
+  const bool vartau = h->base.dtauf != 0.0 || h->base.dtauT != 0.0;
   AdjArgs aa;
   aa.s = h->base;
-  aa.s.nstrips = h->al.nstrips;
-  aa.s.rows_per_chunk = h->al.rows;
+  aa.a = Abuf;
   aa.part = part;
   aa.dtw = tw;
+  aa.ntx = ntx;
+  char *chk0 = base + A.off_chk, *tape0 = base + A.off_tape;
+  char *mom0 = tape0 + (size_t)A.K * A.state_bytes;
   for (int64_t k = nseg - 1; k >= 0; --k) {
     const int64_t m = std::min(K, N - k * K);
+    char *ck = chk0 + (size_t)k * A.state_bytes;
+    // state j of the segment: the checkpoint, then the tape slots (all of
+    // them with c-dependent relaxation times, else two rotating ones)
     auto state = [&](int64_t j) -> void * {
-      return j == 0 ? base + A.off_chk + (size_t)k * A.state_bytes
-                    : base + A.off_tape + (size_t)j * A.state_bytes;
+      if (j == 0) return ck;
+      return tape0 + (size_t)(vartau ? j : (j & 1)) * A.state_bytes;
     };
-    for (int64_t j = 1; j < m; ++j) {
-      const int rc = launch_step(h, kStore, state(j - 1), state(j), nullptr, nullptr, nullptr,
-                                 nullptr, nullptr);
+    auto moments = [&](int64_t j) -> void * { return mom0 + (size_t)j * A.mom_bytes; };
+    for (int64_t j = 0; j < m; ++j) {
+      const bool last = j + 1 == m;   // its successor is not needed
+      const int rc = launch_step(h, last ? kTape : (kStore | kTape), state(j),
+                                 last ? nullptr : state(j + 1), nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, moments(j));
       if (rc != LBE_CSF_OK) return rc;
     }
     for (int64_t j = m - 1; j >= 0; --j) {
-      aa.s.src = state(j);
-      aa.lam_in = lam[cur];
-      aa.lam_out = lam[1 - cur];
-      if (f64) launch_adj<double, false>(h->al, aa, st);
-      else launch_adj<float, true>(h->al, aa, st);
+      aa.s.src = vartau ? state(j) : nullptr;
+      aa.s.tape = moments(j);
+      aa.d_in = D[cur];
+      aa.m_in = M[cur];
+      aa.d_out = D[1 - cur];
+      aa.m_out = M[1 - cur];
+      if (f64) launch_adj<double, false>(vartau, aa, nb, st);
+      else launch_adj<float, true>(vartau, aa, nb, st);
       HIPCHK(h, hipGetLastError());
       cur = 1 - cur;
     }
@@ -375,10 +371,12 @@ int run_backward(lbe_csf *h, const double *dJdc, double *dsT, double *dTw, doubl
   const unsigned g1 = (unsigned)((n + 255) / 256);
   if (dF0 || dT0) {
     if (f64)
-      adj_finish_kernel<double><<<g1, 256, 0, st>>>(static_cast<const double *>(lam[cur]), dF0,
+      adj_finish_kernel<double><<<g1, 256, 0, st>>>(static_cast<const double *>(D[cur]),
+                                                    static_cast<const double *>(M[cur]), dF0,
                                                     dT0, n, h->base.rcv);
     else
-      adj_finish_kernel<float><<<g1, 256, 0, st>>>(static_cast<const float *>(lam[cur]), dF0,
+      adj_finish_kernel<float><<<g1, 256, 0, st>>>(static_cast<const float *>(D[cur]),
+                                                   static_cast<const float *>(M[cur]), dF0,
                                                    dT0, n, h->base.rcv);
   }
   adj_sum_kernel<<<1, 256, 0, st>>>(part, nb, outv);
@@ -439,7 +437,6 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   h->P = *params;
   h->L = L;
   h->la = pick_launch(params->nx, params->ny, L.state_bytes);
-  h->al = pick_adj_launch(params->nx, params->ny, params->precision == LBE_CSF_FP64);
   h->stream = static_cast<hipStream_t>(stream);
   h->ws = static_cast<char *>(workspace);
   h->state[0] = h->ws + L.off_a;

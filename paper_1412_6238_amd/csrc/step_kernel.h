@@ -138,6 +138,16 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     if (kEx[q] != 0) jx += R(kEx[q]) * cur.v[q];
     if (kEy[q] != 0) jy += R(kEy[q]) * cur.v[q];
   }
+  if (MODE & kTape) {
+    const size_t s = (size_t)j * nx + x;
+    double *tc = static_cast<double *>(a.tape);
+    R *tr = reinterpret_cast<R *>(tc + n);
+    tc[s] = cd;
+    tr[s] = Tv;
+    tr[n + s] = pv;
+    tr[2 * n + s] = jx;
+    tr[3 * n + s] = jy;
+  }
   // closures
   const R Tm = DEV ? Tv + k.TsmTref : Tv - k.Tref;   // T - Tref
   const R sigma = k.sigma0 - k.sigmaT * Tm;

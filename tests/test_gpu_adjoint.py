@@ -65,21 +65,28 @@ def _rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
+# relaxation times that vary with c use the full-state replay; constant ones
+# the moment tape
+CONST_TAU = dict(tau_f=(0.9, 0.9), tau_T=(0.8, 0.8))
 CASES = [
-    # nx, ny, walls, seed, N, precision
-    (37, 21, 1, 5, 12, "fp64"),
-    (130, 13, 1, 11, 10, "fp64"),
-    (70, 9, 0, 7, 12, "fp64"),
-    (37, 21, 1, 5, 12, "fp32_dev"),
-    (130, 13, 1, 11, 10, "fp32_dev"),
+    # nx, ny, walls, seed, N, precision, parameter overrides
+    (37, 21, 1, 5, 12, "fp64", {}),
+    (130, 13, 1, 11, 10, "fp64", {}),
+    (70, 9, 0, 7, 12, "fp64", {}),
+    (37, 21, 1, 5, 12, "fp32_dev", {}),
+    (130, 13, 1, 11, 10, "fp32_dev", {}),
+    (37, 21, 1, 5, 12, "fp64", CONST_TAU),
+    (130, 13, 1, 11, 10, "fp64", CONST_TAU),
+    (70, 9, 0, 7, 12, "fp64", CONST_TAU),
+    (130, 13, 1, 11, 10, "fp32_dev", CONST_TAU),
 ]
 
 
-@pytest.mark.parametrize("nx,ny,walls,seed,N,prec", CASES)
-def test_adjoint_vs_oracle_fd(lbe, oracle_mod, nx, ny, walls, seed, N, prec):
+@pytest.mark.parametrize("nx,ny,walls,seed,N,prec,over", CASES)
+def test_adjoint_vs_oracle_fd(lbe, oracle_mod, nx, ny, walls, seed, N, prec, over):
     import torch
-    _say(f"adjoint vs oracle FD: {nx}x{ny} walls={walls} seed={seed} N={N} {prec}")
-    case = wl.random_case(nx, ny, seed, walls_y=walls)
+    _say(f"adjoint vs oracle FD: {nx}x{ny} walls={walls} seed={seed} N={N} {prec} {over}")
+    case = wl.random_case(nx, ny, seed, walls_y=walls, **over)
     rng = np.random.default_rng(1000 + seed)
     s = rng.standard_normal((ny, nx))
     # weights near the walls make the wall-temperature derivative sizeable
@@ -132,6 +139,27 @@ def test_adjoint_vs_oracle_fd(lbe, oracle_mod, nx, ny, walls, seed, N, prec):
             assert _rel(ad, fd) <= tol
     else:
         assert np.all(g["Twall"] == 0.0)
+
+
+def test_tape_matches_full_state(lbe, monkeypatch):
+    """With constant relaxation times the moment-tape adjoint and the
+    full-state adjoint linearise at the same point: FP64 gradients agree to
+    round-off."""
+    import torch
+    case = wl.random_case(130, 13, 9, walls_y=1, **CONST_TAU)
+    seed = torch.as_tensor(np.random.default_rng(6).standard_normal((13, 130)))
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("LBE_CSF_ADJ_TAPE", flag)
+        sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                             case["Twall_top"], precision="fp64", record_steps=23)
+        sim.step(23, record=True)
+        out.append(sim.backward(seed, want_F0=True))
+    a, b = out
+    assert _rel(a["sigmaT"], b["sigmaT"]) <= 1e-12
+    for k in ("Twall", "F0", "T0"):
+        d = (a[k] - b[k]).abs().max().item()
+        assert d <= 1e-12 * b[k].abs().max().item(), (k, d)
 
 
 def test_adjoint_deterministic_and_state_kept(lbe):

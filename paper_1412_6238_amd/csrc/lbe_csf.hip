@@ -48,16 +48,12 @@ Launch pick_launch(int nx, int ny, size_t state_bytes) {
   L.pipe = 1;
   if (const char *e = std::getenv("LBE_CSF_PIPE")) {
     const int v = std::atoi(e);
-    if (v == 0 || v == 1 || v == 3) L.pipe = v;
+    if (v == 0 || v == 1) L.pipe = v;
   }
-  // the LDS-fed kernel moves 16-byte chunks (x a multiple of 4 keeps them
-  // aligned) through one buffer descriptor (state below 4 GiB)
-  if (L.pipe == 3 && nx % 4 != 0) L.pipe = 1;
   L.nw = nx >= 2048 ? 4 : (nx >= 256 ? 2 : 1);
-  if (L.pipe == 3) L.nw = 1;
   if (const char *e = std::getenv("LBE_CSF_NW")) {
     const int v = std::atoi(e);
-    if (v == 1 || v == 2 || (v == 4 && L.pipe != 3)) L.nw = v;
+    if (v == 1 || v == 2 || v == 4) L.nw = v;
   }
   const int bx = 64 * L.nw;
   L.nstrips = (nx + bx - 1) / bx;
@@ -227,18 +223,9 @@ void launch_pipe(const Launch &la, const StepArgs &a, hipStream_t st) {
 }
 
 template <typename S, typename R, bool DEV, int MODE>
-void launch_lds(const Launch &la, const StepArgs &a, hipStream_t st) {
-  switch (la.nw) {
-    case 1: step_kernel_lds<S, R, DEV, MODE, 1><<<la.nblocks, 128, 0, st>>>(a); break;
-    default: step_kernel_lds<S, R, DEV, MODE, 2><<<la.nblocks, 192, 0, st>>>(a); break;
-  }
-}
-
-template <typename S, typename R, bool DEV, int MODE>
 void launch_mode(const Launch &la, const StepArgs &a, hipStream_t st) {
   switch (la.pipe) {
     case 0: launch_pipe<S, R, DEV, MODE, 0>(la, a, st); break;
-    case 3: launch_lds<S, R, DEV, MODE>(la, a, st); break;
     default: launch_pipe<S, R, DEV, MODE, 1>(la, a, st); break;
   }
 }

@@ -27,15 +27,10 @@
 // Work decomposition: a block owns a strip of 64*NW columns and marches up a
 // chunk of rows, one column per lane.  The moments a row's stencils need
 // (c, T, p) sit in an LDS ring of four rows, filled one row ahead of the row
-// being collided; helper lanes add the halo column on each side.  Two ways of
-// feeding rows are provided:
-//   step_kernel      rows are loaded into registers one row ahead (PIPE 1)
-//                    or loaded twice, for the moments and again for the
-//                    collision (PIPE 0);
-//   step_kernel_lds  one extra wave per block streams rows straight into LDS
-//                    (buffer_load ... lds) up to three rows ahead of the
-//                    collision, so the depth of the prefetch costs no
-//                    registers.
+// being collided; helper lanes add the halo column on each side.  PIPE 1
+// keeps the next row's values in registers, loaded one row ahead of the
+// collision; PIPE 0 loads a row twice (for the moments and again, from
+// cache, for the collision).
 // Either way every distribution is read from HBM once per step (halo columns
 // and the two boundary rows of a chunk are re-read from cache).
 //
@@ -444,263 +439,6 @@ step_kernel(const StepArgs a) {
   }
   if (MODE & kDiag)
     block_partials<NW>(acc, red, lane, a.partials + (size_t)blockIdx.x * kNumPartials);
-}
-
-// ---------------------------------------------------------------------------
-// LDS-fed variant: NW compute waves plus one loader wave per block.
-//
-// The loader streams each row straight into LDS with 16-byte buffer_load ...
-// lds operations (64 lanes x 16 B = 1 KiB each) and stays ahead: row r uses
-// slot r % 4; while row j collides, row j + 1 is resident (its moments are
-// in the ring), row j + 2 is landing and row j + 3 has just been issued.  The
-// loader issues loads only, so it can wait for the older row with a counted
-// vmcnt.  Compute waves read their own column from LDS and never load from
-// memory.
-//
-// One wave-row in LDS: 25 planes x 64 x sizeof(S), then g_0 and hbar_0 (64
-// doubles each), padded to whole KiB.  The halo (the column on each side of
-// the strip) follows the NW wave-rows as single dwords: 25 values per side,
-// then g_0 and hbar_0 of both sides.
-template <typename S>
-struct LdsGeom {
-  static constexpr int kPlaneBytes = 64 * (int)sizeof(S);
-  static constexpr int kRowBytes = kNumS * kPlaneBytes + 2 * 512;           // real bytes
-  static constexpr int kInstr = (kRowBytes + 1023) / 1024;                  // 16-B DMA per lane
-  static constexpr int kRowPad = kInstr * 1024;
-  static constexpr int kValDw = (int)(sizeof(S) / 4);                        // dwords per value
-  static constexpr int kHaloDw = 2 * kNumS * kValDw + 8;
-  static constexpr int kHaloInstr = (kHaloDw + 63) / 64;
-  static constexpr int kHaloPad = kHaloInstr * 64 * 4;                      // bytes
-};
-
-// Workgroup barrier for the LDS-fed kernel.  Every wave first waits for its
-// own LDS writes (ring entries); the loader has already waited, with a counted
-// vmcnt, for the rows the others read next.  Written out so that no implicit
-// wait for all outstanding loads is placed before it, which would drain the
-// loader's prefetch at every barrier.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-template <typename S, typename R, bool DEV, int MODE, int NW>
-__global__ void __launch_bounds__(64 * (NW + 1))
-step_kernel_lds(const StepArgs a) {
-  using G = LdsGeom<S>;
-  constexpr int BX = 64 * NW;
-  constexpr int NBUF = 4;
-  constexpr int kSlot = NW * G::kRowPad + G::kHaloPad;
-  __shared__ __attribute__((aligned(16))) char vals[NBUF * kSlot];
-  __shared__ double ringc[4][BX + 2];
-  __shared__ R ringt[4][BX + 2];
-  __shared__ R ringp[4][BX + 2];
-  __shared__ double red[NW + 1][kNumPartials];
-
-  const int nx = a.nx, ny = a.ny;
-  const bool walls = a.walls_y != 0;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
-  const int strip = t % a.nstrips;
-  const int chunk = t / a.nstrips;
-  const int x0 = strip * BX;
-  const int nact = min(BX, nx - x0);
-  const int lane = threadIdx.x;
-  const int wave = lane >> 6, wl = lane & 63;
-  const bool loader = wave == NW;
-  const bool act = !loader && lane < nact;
-  const int x = x0 + lane;
-  const int y0 = chunk * a.rows_per_chunk;
-  const int y1 = min(y0 + a.rows_per_chunk, ny);
-  const size_t n = (size_t)nx * (size_t)ny;
-  const Consts<R> k(a);
-  const double inv_rcv = 1.0 / a.rcv;
-  const int hx0 = x0 == 0 ? nx - 1 : x0 - 1;
-  const int hx1 = x0 + nact == nx ? 0 : x0 + nact;
-
-  auto wrap_row = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
-  auto is_ghost = [&](int row) { return walls && (row < 0 || row >= ny); };
-  auto slot_of = [&](int row) { return vals + (row & (NBUF - 1)) * kSlot; };
-
-  // ---- loader: row `row` (unwrapped index, for the slot) of the strip and
-  // its halo columns; the whole state is one buffer resource (< 2^32 bytes)
-  const __amdgpu_buffer_rsrc_t rs = plane_rsrc(a.src, kNumS * n * sizeof(S) + 2 * n * 8);
-  const uint32_t dbase = (uint32_t)(kNumS * n * sizeof(S));   // first FP64 plane
-  auto issue_row = [&](int row) {
-    char *slot = slot_of(row);
-    const uint32_t rbase = (uint32_t)wrap_row(row) * (uint32_t)nx;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const uint32_t col0 = rbase + (uint32_t)(x0 + 64 * w);   // site of the wave's lane 0
-#pragma unroll
-      for (int i = 0; i < G::kInstr; ++i) {
-        const int b = (i * 64 + wl) * 16;   // byte of this lane's chunk in the wave-row
-        uint32_t off;
-        if (b < kNumS * G::kPlaneBytes) {
-          const int pl = b / G::kPlaneBytes, bo = b % G::kPlaneBytes;
-          off = (uint32_t)(pl * n * sizeof(S)) + col0 * (uint32_t)sizeof(S) + (uint32_t)bo;
-        } else if (b < G::kRowBytes) {
-          const int db = b - kNumS * G::kPlaneBytes;
-          off = dbase + (uint32_t)((db / 512) * n * 8) + col0 * 8u + (uint32_t)(db % 512);
-        } else {
-          off = col0 * (uint32_t)sizeof(S);   // padding: any in-range bytes
-        }
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-            rs, (__attribute__((address_space(3))) void *)(slot + w * G::kRowPad + i * 1024), 16,
-            off, 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < G::kHaloInstr; ++i) {
-      const int d = i * 64 + wl;
-      uint32_t off;
-      if (d < 2 * kNumS * G::kValDw) {
-        const int e = d / G::kValDw, half = d % G::kValDw;
-        const int side = e / kNumS, pl = e % kNumS;
-        const uint32_t col = rbase + (uint32_t)(side ? hx1 : hx0);
-        off = (uint32_t)(pl * n * sizeof(S)) + col * (uint32_t)sizeof(S) + half * 4u;
-      } else if (d < G::kHaloDw) {
-        const int dd = d - 2 * kNumS * G::kValDw;            // 0..7
-        const int which = dd / 4, side = (dd / 2) % 2, half = dd % 2;
-        const uint32_t col = rbase + (uint32_t)(side ? hx1 : hx0);
-        off = dbase + (uint32_t)(which * n * 8) + col * 8u + half * 4u;
-      } else {
-        off = 0;
-      }
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rs, (__attribute__((address_space(3))) void *)(slot + NW * G::kRowPad + i * 256), 4, off,
-          0, 0, 0);
-    }
-  };
-  constexpr int kRowOps = NW * G::kInstr + G::kHaloInstr;
-  static_assert(kRowOps <= 63, "vmcnt range");
-  // gfx9 s_waitcnt immediate: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8
-  constexpr int kWaitRow = (kRowOps & 0xF) | ((kRowOps >> 4) << 14) | (0x7 << 4) | (0xF << 8);
-  constexpr int kWaitAll = (0x7 << 4) | (0xF << 8);
-  auto needs_load = [&](int row) { return row >= y0 - 1 && row <= y1 && !is_ghost(row); };
-
-  // ---- compute waves
-  auto read_row = [&](int row, RowVals<R> &r) {
-    const char *base = slot_of(row) + wave * G::kRowPad;
-#pragma unroll
-    for (int q = 0; q < 27; ++q)
-      if (q != 9 && q != 18)
-        r.v[q] = R(reinterpret_cast<const S *>(base + plane_of(q) * G::kPlaneBytes)[wl]);
-    const double *d = reinterpret_cast<const double *>(base + kNumS * G::kPlaneBytes);
-    r.g0 = d[wl];
-    r.h0 = d[64 + wl];
-  };
-  // helper lanes 0..5 of wave 0: halo moments from the slot
-  const bool helper = wave == 0 && wl < 6;
-  const int hside = wl / 3, hfield = wl - 3 * (wl / 3);
-  const int hpos = hside == 0 ? 0 : nact + 1;
-  auto halo_value = [&](const char *slot, int q) -> R {
-    const S *h = reinterpret_cast<const S *>(slot + NW * G::kRowPad);
-    return R(h[hside * kNumS + plane_of(q)]);
-  };
-  auto halo_double = [&](const char *slot, int which) -> double {
-    const double *h = reinterpret_cast<const double *>(slot + NW * G::kRowPad +
-                                                       2 * kNumS * sizeof(S));
-    return h[which * 2 + hside];
-  };
-  auto put_moments = [&](int row) {
-    const int rs4 = row & 3;
-    if (act) {
-      RowVals<R> r;
-      read_row(row, r);
-      double c, T;
-      R p;
-      site_moments(r, inv_rcv, &c, &T, &p);
-      ringc[rs4][lane + 1] = c;
-      ringt[rs4][lane + 1] = R(T);
-      ringp[rs4][lane + 1] = p;
-    }
-    if (helper) {
-      const char *sl = slot_of(row);
-      if (hfield == 0) {
-        R cs = 0;
-#pragma unroll
-        for (int q = 1; q < 9; ++q) cs += halo_value(sl, 9 + q);
-        ringc[rs4][hpos] = halo_double(sl, 0) + double(cs);
-      } else if (hfield == 1) {
-        R hs = 0;
-#pragma unroll
-        for (int q = 1; q < 9; ++q) hs += halo_value(sl, 18 + q);
-        ringt[rs4][hpos] = R((halo_double(sl, 1) + double(hs)) * inv_rcv);
-      } else {
-        R f = 0;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) f += halo_value(sl, q);
-        ringp[rs4][hpos] = f;
-      }
-    }
-  };
-  auto put_ghost = [&](int row, int from) {
-    const int s4 = row & 3, f4 = from & 3;
-    const double *tw = row < 0 ? a.twb : a.twt;
-    if (act) {
-      ringc[s4][lane + 1] = ringc[f4][lane + 1];
-      ringp[s4][lane + 1] = ringp[f4][lane + 1];
-      const R twv = DEV ? R(tw[x] - a.Ts) : R(tw[x]);
-      ringt[s4][lane + 1] = R(2) * twv - ringt[f4][lane + 1];
-    }
-    if (helper) {
-      if (hfield == 0) {
-        ringc[s4][hpos] = ringc[f4][hpos];
-      } else if (hfield == 1) {
-        const int hxs = hside ? hx1 : hx0;
-        const R twv = DEV ? R(tw[hxs] - a.Ts) : R(tw[hxs]);
-        ringt[s4][hpos] = R(2) * twv - ringt[f4][hpos];
-      } else {
-        ringp[s4][hpos] = ringp[f4][hpos];
-      }
-    }
-  };
-  auto moments_or_ghost = [&](int row, int adj) {
-    if (is_ghost(row)) put_ghost(row, adj);
-    else put_moments(row);
-  };
-
-  double acc[kNumPartials];
-#pragma unroll
-  for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
-
-  // prologue: the loader issues rows y0 - 1 .. y0 + 2 and waits for all but
-  // the last one issued; compute waves then put rows y0 - 1 and y0 in the ring
-  if (loader) {
-    for (int r = y0 - 1; r <= y0 + 2; ++r)
-      if (needs_load(r)) issue_row(r);
-    if (needs_load(y0 + 2)) __builtin_amdgcn_s_waitcnt(kWaitRow);
-    else __builtin_amdgcn_s_waitcnt(kWaitAll);
-  }
-  lds_barrier();
-  if (!loader) {
-    put_moments(y0);
-    moments_or_ghost(y0 - 1, y0);
-  }
-  for (int j = y0; j < y1; ++j) {
-    // moments of row j + 1 (landed); then the ring holds rows j - 1 .. j + 1
-    if (!loader) moments_or_ghost(j + 1, j);
-    lds_barrier();
-    if (loader) {
-      // row j - 1's slot is free: issue row j + 3, then wait for row j + 2
-      if (needs_load(j + 3)) {
-        issue_row(j + 3);
-        __builtin_amdgcn_s_waitcnt(kWaitRow);
-      } else {
-        __builtin_amdgcn_s_waitcnt(kWaitAll);
-      }
-    } else if (act) {
-      RowVals<R> cur;
-      read_row(j, cur);
-      const int l = lane;
-      site_update<S, R, DEV, MODE>(a, k, j, x, &ringc[(j - 1) & 3][l], &ringc[j & 3][l],
-                                   &ringc[(j + 1) & 3][l], &ringt[(j - 1) & 3][l],
-                                   &ringt[j & 3][l], &ringt[(j + 1) & 3][l],
-                                   &ringp[(j - 1) & 3][l], &ringp[j & 3][l],
-                                   &ringp[(j + 1) & 3][l], cur, acc);
-    }
-    lds_barrier();
-  }
-  if (MODE & kDiag)
-    block_partials<NW + 1>(acc, red, lane, a.partials + (size_t)blockIdx.x * kNumPartials);
 }
 
 }  // namespace lbe

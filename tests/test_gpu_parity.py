@@ -47,12 +47,15 @@ def _cmp(gpu, orc, tol=1e-12, what=""):
     if "ux" in o:
         g["u"] = np.stack([g.pop("ux"), g.pop("uy")])
         o["u"] = np.stack([o.pop("ux"), o.pop("uy")])
+    errs = {}
     for k in o:
         gk, ok = np.asarray(g[k]), np.asarray(o[k])
         scale = max(np.abs(ok).max(), 1e-300)
         assert np.all(np.isfinite(gk)), (what, k)
-        assert _rel(gk, ok) <= tol, (what, k, _rel(gk, ok))
+        errs[k] = _rel(gk, ok)
+        assert errs[k] <= tol, (what, k, errs[k])
         assert np.abs(gk - ok).max() <= 10 * tol * scale, (what, k, np.abs(gk - ok).max() / scale)
+    _say(f"  {what}: rel L2 " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
 
 
 def _fields_np(sim):
@@ -149,11 +152,11 @@ def test_fp64_workloads(lbe, oracle_mod, name, nsteps, p0):
     _cmp(g, o, what=name)
 
 
-@pytest.mark.parametrize("pipe", ["0", "1", "3"])
+@pytest.mark.parametrize("pipe", ["0", "1"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
 def test_row_pipelines_agree(lbe, oracle_mod, monkeypatch, pipe, precision):
-    """The three ways of feeding rows (two register pipelines and the LDS-fed
-    kernel with its loader wave) give the same state, bit for bit, and FP64
+    """The two ways of feeding rows (gathered values kept one row ahead in
+    registers, or gathered twice) give the same state, bit for bit, and FP64
     matches the oracle."""
     case = wl.random_case(136, 40, seed=21, walls_y=1)
     monkeypatch.setenv("LBE_CSF_PIPE", pipe)

@@ -63,8 +63,9 @@ typedef enum {
 typedef enum {
   LBE_CSF_FP64 = 0,     /* distributions stored and evolved in FP64            */
   LBE_CSF_FP32_DEV = 1  /* FP32 deviations from the rest-weight equilibrium:
-                           f - w p0, g, hbar - w rho cv T_shift (FP64 sums for
-                           the diagnostics)                                  */
+                           f - w p0, g, hbar - w rho cv T_ref(y) with the
+                           linear reference T_ref = T_shift + T_grad y (FP64
+                           g_0, hbar_0 and FP64 sums for the diagnostics)    */
 } lbe_csf_precision;
 
 /* Parameters (plain data; lattice units, dt = dx = 1, cs^2 = 1/3). */
@@ -85,7 +86,11 @@ typedef struct {
   double sigma0, sigmaT, Tref; /* sigma = sigma0 - sigmaT (T - Tref)           */
   double force[2];       /* body acceleration a (adds rho a to F)             */
   double p0;             /* pressure of the initial state                     */
-  double T_shift;        /* FP32_DEV: temperature the hbar deviations refer to */
+  double T_shift;        /* FP32_DEV: the hbar deviations refer to the linear  */
+  double T_grad;         /* temperature T_ref(y) = T_shift + T_grad y (a
+                            background close to the expected field, such as
+                            the conduction profile between the walls, keeps
+                            the stored deviations and their rounding small)  */
   int32_t diag_every;    /* > 0: diagnostics of every diag_every-th state
                             during lbe_csf_step (kept on the device, fetched
                             by lbe_csf_diag_history); 0: none               */

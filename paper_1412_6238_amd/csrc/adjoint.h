@@ -124,12 +124,12 @@ struct AdjArgs {
 template <typename R, bool DEV, bool VARTAU>
 __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> &k,
                                              const RowVals<R> &cur, R p, R jx, R jy, double Td,
-                                             double cd, R gcx, R gcy, R lapc, R gTx, R gTy,
-                                             R gpx, R gpy, const R *lam, R *db, R *da,
-                                             double *dsT) {
+                                             double Trow, double cd, R gcx, R gcy, R lapc,
+                                             R gTx, R gTy, R gpx, R gpy, const R *lam, R *db,
+                                             R *da, double *dsT) {
   const R third = R(1) / R(3);
   const R c = R(cd);
-  const double Tfull_d = DEV ? Td + a.Ts : Td;
+  const double Tfull_d = DEV ? Td + Trow : Td;
   const R Tv = R(Td), Tfull = R(Tfull_d);
   const R mu = R(a.beta2 * cd * (cd - 1.0) * (2.0 * cd - 1.0) - a.eps2 * double(lapc));
   const R Tm = R(Tfull_d - a.Tref);
@@ -304,7 +304,8 @@ adj_collide_kernel(const AdjArgs aa) {
     if (walls && (row < 0 || row >= ny)) {
       const size_t s = (size_t)(row < 0 ? 0 : ny - 1) * nx + col;
       const double *tw = row < 0 ? a.twb : a.twt;
-      const R twv = DEV ? R(tw[col] - a.Ts) : R(tw[col]);
+      const double twref = DEV ? a.Ts + (row < 0 ? 0.0 : a.Tg * double(ny)) : 0.0;
+      const R twv = DEV ? R(tw[col] - twref) : R(tw[col]);
       lc[r][q] = tape_c[s];
       lp[r][q] = tape_r[n + s];
       lt[r][q] = R(2) * twv - tape_r[s];
@@ -383,6 +384,8 @@ adj_collide_kernel(const AdjArgs aa) {
     R gTx, gTy, gpx, gpy;
     grad(lt, &gTx, &gTy);
     grad(lp, &gpx, &gpy);
+    if (DEV) gTy += R(a.Tg);   // linear temperature reference of the FP32 form
+    const double Trow = DEV ? a.Ts + a.Tg * (double(y) + 0.5) : 0.0;
     RowVals<R> cur;
     if (VARTAU) {
       const __amdgpu_buffer_rsrc_t rs =
@@ -396,8 +399,8 @@ adj_collide_kernel(const AdjArgs aa) {
     }
     R db[27], da[7];
     site_adjoint<R, DEV, VARTAU>(a, k, cur, lp[cy][cx], tape_r[2 * n + s], tape_r[3 * n + s],
-                                 double(lt[cy][cx]), cd, R(gcx_d), R(gcy_d), R(lap_d), gTx,
-                                 gTy, gpx, gpy, lam, db, da, &ds);
+                                 double(lt[cy][cx]), Trow, cd, R(gcx_d), R(gcy_d), R(lap_d),
+                                 gTx, gTy, gpx, gpy, lam, db, da, &ds);
     const __amdgpu_buffer_rsrc_t wd = plane_rsrc(aa.d_out, 27 * n * sizeof(R));
     const __amdgpu_buffer_rsrc_t wa = plane_rsrc(aa.a, 7 * n * sizeof(R));
 #pragma unroll

@@ -9,14 +9,15 @@ namespace lbe {
 // Initial state: u = 0, p = p0, c0 = (1 + phi0)/2, mu0 from c0 and its
 // nine-point Laplacian (mirror ghosts at walls), every distribution at its
 // equilibrium (Sec. II Eqs. 7, 13-14; Sec. III Eq. 22).  FP32 form: stored as
-// deviations, so f - w p0 = 0 and hbar - w rho cv Ts = w rho cv (T0 - Ts).
+// deviations, so f - w p0 = 0 and hbar - w rho cv Tr = w rho cv (T0 - Tr)
+// with the linear reference Tr = Ts + Tg (y + 1/2) of the site's row.
 // Layout as in step_kernel.h: 25 planes of S, then FP64 g_0 and hbar_0.
 template <typename S, bool DEV>
 __global__ void __launch_bounds__(256)
 init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
             const double *__restrict__ T0, int nx, int ny, int walls_y,
             double beta2, double eps2, double gam3, double rcv, double p0,
-            double Ts) {
+            double Ts, double Tg) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= nx || y >= ny) return;
@@ -42,11 +43,12 @@ init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
   const double mu = beta2 * c * (c - 1.0) * (2.0 * c - 1.0) - eps2 * lap;
   const double gmu = gam3 * mu;
   const double T = T0[s];
+  const double Tr = Ts + Tg * (y + 0.5);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const double w = wq<double>(i);
     F[plane_of(i) * n + s] = DEV ? S(0) : S(w * p0);
-    const double hv = DEV ? w * rcv * (T - Ts) : w * rcv * T;
+    const double hv = DEV ? w * rcv * (T - Tr) : w * rcv * T;
     if (i == 0) {
       Fd[s] = c - (1.0 - w) * gmu;
       Fd[n + s] = hv;
@@ -106,7 +108,7 @@ diag_reduce_kernel(const double *__restrict__ partials, int nblocks,
 template <typename S, bool DEV>
 __global__ void __launch_bounds__(256)
 state_to_f64(const S *__restrict__ F, double *__restrict__ out, int nx, int ny,
-             double p0, double rcvTs) {
+             double p0, double rcv, double Ts, double Tg) {
   const size_t n = (size_t)nx * ny;
   const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
@@ -116,7 +118,7 @@ state_to_f64(const S *__restrict__ F, double *__restrict__ out, int nx, int ny,
   double v = q == 9 ? Fd[s] : (q == 18 ? Fd[n + s] : double(F[plane_of(q) * n + s]));
   if (DEV) {
     if (q < 9) v += wq<double>(i) * p0;
-    else if (q >= 18) v += wq<double>(i) * rcvTs;
+    else if (q >= 18) v += wq<double>(i) * rcv * (Ts + Tg * (double(s / nx) + 0.5));
   }
   out[q * n + s] = v;
 }
@@ -124,7 +126,7 @@ state_to_f64(const S *__restrict__ F, double *__restrict__ out, int nx, int ny,
 template <typename S, bool DEV>
 __global__ void __launch_bounds__(256)
 state_from_f64(S *__restrict__ F, const double *__restrict__ in, int nx, int ny,
-               double p0, double rcvTs) {
+               double p0, double rcv, double Ts, double Tg) {
   const size_t n = (size_t)nx * ny;
   const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
@@ -133,7 +135,7 @@ state_from_f64(S *__restrict__ F, const double *__restrict__ in, int nx, int ny,
   double v = in[q * n + s];
   if (DEV) {
     if (q < 9) v -= wq<double>(i) * p0;
-    else if (q >= 18) v -= wq<double>(i) * rcvTs;
+    else if (q >= 18) v -= wq<double>(i) * rcv * (Ts + Tg * (double(s / nx) + 0.5));
   }
   double *Fd = reinterpret_cast<double *>(F + kNumS * n);
   if (q == 9) Fd[s] = v;

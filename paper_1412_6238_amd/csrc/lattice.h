@@ -51,7 +51,8 @@ struct StepArgs {
   double kcap, epsalpha;    // alpha/eps and eps*alpha
   double sigma0, sigmaT, Tref;
   double ax, ay;            // body acceleration
-  double p0, Ts;            // deviation references (FP32 form)
+  double p0, Ts, Tg;        // deviation references (FP32 form): w p0 for f,
+                            // w rho cv (Ts + Tg y) for hbar at height y
   // outputs
   double *phi, *ux, *uy, *p, *T;
   double *partials;         // [gridDim.x][kNumPartials]

@@ -104,7 +104,7 @@ bool params_valid(const lbe_csf_params *p, std::string *why) {
   if (!(p->width > 0) || !fin(p->width)) return bad("width must be > 0");
   if (!(p->beta > 0) || !fin(p->beta)) return bad("beta must be > 0");
   if (!fin(p->sigma0) || !fin(p->sigmaT) || !fin(p->Tref) || !fin(p->force[0]) ||
-      !fin(p->force[1]) || !fin(p->p0) || !fin(p->T_shift))
+      !fin(p->force[1]) || !fin(p->p0) || !fin(p->T_shift) || !fin(p->T_grad))
     return bad("non-finite parameter");
   if (p->diag_every < 0) return bad("diag_every must be >= 0");
   if (p->reserved != 0) return bad("reserved must be 0");
@@ -210,6 +210,7 @@ void fill_constants(lbe_csf *h) {
   a.ay = p.force[1];
   a.p0 = p.precision == LBE_CSF_FP32_DEV ? p.p0 : 0.0;
   a.Ts = p.precision == LBE_CSF_FP32_DEV ? p.T_shift : 0.0;
+  a.Tg = p.precision == LBE_CSF_FP32_DEV ? p.T_grad : 0.0;
   a.partials = h->partials;
 }
 
@@ -465,11 +466,11 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   if (params->precision == LBE_CSF_FP64)
     init_kernel<double, false><<<grid, 256, 0, h->stream>>>(
         static_cast<double *>(h->state[0]), phi0, T0, nx, ny, params->walls_y, beta2, eps2,
-        gam3, h->base.rcv, params->p0, 0.0);
+        gam3, h->base.rcv, params->p0, 0.0, 0.0);
   else
     init_kernel<float, true><<<grid, 256, 0, h->stream>>>(
         static_cast<float *>(h->state[0]), phi0, T0, nx, ny, params->walls_y, beta2, eps2,
-        gam3, h->base.rcv, params->p0, params->T_shift);
+        gam3, h->base.rcv, params->p0, params->T_shift, params->T_grad);
   e = hipGetLastError();
   if (e != hipSuccess) {
     h->err = std::string("init kernel: ") + hipGetErrorString(e);
@@ -575,13 +576,13 @@ int lbe_csf_get_state(lbe_csf *h, double *F) {
   if (!F) return fail(h, LBE_CSF_EINVAL, "F is NULL");
   const size_t n = (size_t)h->P.nx * h->P.ny;
   dim3 grid((unsigned)((n + 255) / 256), 27);
-  const double rcvTs = h->base.rcv * h->base.Ts;
   if (h->P.precision == LBE_CSF_FP64)
     state_to_f64<double, false><<<grid, 256, 0, h->stream>>>(
-        static_cast<const double *>(h->state[h->cur]), F, h->P.nx, h->P.ny, 0.0, 0.0);
+        static_cast<const double *>(h->state[h->cur]), F, h->P.nx, h->P.ny, 0.0, 0.0, 0.0, 0.0);
   else
     state_to_f64<float, true><<<grid, 256, 0, h->stream>>>(
-        static_cast<const float *>(h->state[h->cur]), F, h->P.nx, h->P.ny, h->base.p0, rcvTs);
+        static_cast<const float *>(h->state[h->cur]), F, h->P.nx, h->P.ny, h->base.p0,
+        h->base.rcv, h->base.Ts, h->base.Tg);
   HIPCHK(h, hipGetLastError());
   return LBE_CSF_OK;
 }
@@ -591,13 +592,13 @@ int lbe_csf_set_state(lbe_csf *h, const double *F) {
   if (!F) return fail(h, LBE_CSF_EINVAL, "F is NULL");
   const size_t n = (size_t)h->P.nx * h->P.ny;
   dim3 grid((unsigned)((n + 255) / 256), 27);
-  const double rcvTs = h->base.rcv * h->base.Ts;
   if (h->P.precision == LBE_CSF_FP64)
     state_from_f64<double, false><<<grid, 256, 0, h->stream>>>(
-        static_cast<double *>(h->state[h->cur]), F, h->P.nx, h->P.ny, 0.0, 0.0);
+        static_cast<double *>(h->state[h->cur]), F, h->P.nx, h->P.ny, 0.0, 0.0, 0.0, 0.0);
   else
     state_from_f64<float, true><<<grid, 256, 0, h->stream>>>(
-        static_cast<float *>(h->state[h->cur]), F, h->P.nx, h->P.ny, h->base.p0, rcvTs);
+        static_cast<float *>(h->state[h->cur]), F, h->P.nx, h->P.ny, h->base.p0,
+        h->base.rcv, h->base.Ts, h->base.Tg);
   HIPCHK(h, hipGetLastError());
   h->recorded = false;
   return LBE_CSF_OK;

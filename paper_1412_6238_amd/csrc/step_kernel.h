@@ -37,7 +37,10 @@
 // Two arithmetic forms share the templates:
 //   R = double, DEV = false: FP64 values as defined by the paper;
 //   R = float,  DEV = true : FP32 deviations f - w p0, g_{1..8},
-//     hbar_{1..8} - w rho cv Ts (and FP64 g_0, hbar_0 - w0 rho cv Ts);
+//     hbar_{1..8} - w rho cv Tr (and FP64 g_0, hbar_0 - w0 rho cv Tr), with
+//     the linear reference Tr = Ts + Tg y taken at the row of the stored
+//     value (a population moving to the next row changes reference by
+//     w rho cv Tg xi_y);
 //     Delta p and Delta T come from them, and every equilibrium is written as
 //     a deviation (w Delta p + rho cs^2 G, rho cv (Delta T w + T G), with
 //     G = Gamma_i(u) - w_i), so no large value is formed and then subtracted.
@@ -56,12 +59,12 @@ __host__ __device__ constexpr int plane_of(int q) { return q < 9 ? q : (q < 18 ?
 template <typename R>
 struct Consts {
   R rho, inv_rho, rcv, tauf0, dtauf, tauT0, dtauT, wg, gam3, kcap, epsalpha;
-  R sigma0, sigmaT, TsmTref, Tref, bfx, bfy;
+  R sigma0, sigmaT, Tref, bfx, bfy;
   __device__ explicit Consts(const StepArgs &a)
       : rho(R(a.rho)), inv_rho(R(1.0 / a.rho)), rcv(R(a.rcv)), tauf0(R(a.tauf0)),
         dtauf(R(a.dtauf)), tauT0(R(a.tauT0)), dtauT(R(a.dtauT)), wg(R(a.omg_g)),
         gam3(R(a.gam3)), kcap(R(a.kcap)), epsalpha(R(a.epsalpha)), sigma0(R(a.sigma0)),
-        sigmaT(R(a.sigmaT)), TsmTref(R(a.Ts - a.Tref)), Tref(R(a.Tref)),
+        sigmaT(R(a.sigmaT)), Tref(R(a.Tref)),
         bfx(R(a.rho * a.ax)), bfy(R(a.rho * a.ay)) {}
 };
 
@@ -102,7 +105,6 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
                                             double *acc) {
   const int nx = a.nx, ny = a.ny;
   const size_t n = (size_t)nx * (size_t)ny;
-  const R third = R(1) / R(3);
   // order parameter and its stencils in FP64
   const double cd = cC[1];
   double gcx_d, gcy_d, lap_d, mu_d;
@@ -116,22 +118,31 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     mu_d = a.beta2 * cd * (cd - 1.0) * (2.0 * cd - 1.0) - a.eps2 * lap_d;
   }
   const R c = R(cd);
-  const R mu = R(mu_d);
-  const R gcx = R(gcx_d), gcy = R(gcy_d);
-  const R Tv = tC[1];   // T, or Delta T in the FP32 form
+  const R Tv = tC[1];   // T, or Delta T = T - Trow in the FP32 form
   const R pv = pC[1];   // p, or Delta p
-  auto grad = [&](const R *Sr, const R *Cr, const R *Nr, R *gx, R *gy) {
-    *gx = (Cr[2] - Cr[0]) * third + (Nr[2] + Sr[2] - Nr[0] - Sr[0]) * R(1.0 / 12.0);
-    *gy = (Nr[1] - Sr[1]) * third + (Nr[2] + Nr[0] - Sr[2] - Sr[0]) * R(1.0 / 12.0);
+  // FP32 form: temperatures are stored relative to the linear reference
+  // Ts + Tg y; Trow is its value at this row's centre
+  const double Trow = DEV ? a.Ts + a.Tg * (double(j) + 0.5) : 0.0;
+  // Stencils of T and p, the force and the velocity are evaluated in FP64.
+  // Near an interface they are small differences of larger terms (the
+  // capillary force against the pressure gradient in Fbar = F - grad p, the
+  // momentum against the half force in u), so in the FP32 form the
+  // arithmetic, not the storage, would otherwise set the error.
+  auto grad = [&](const R *Sr, const R *Cr, const R *Nr, double *gx, double *gy) {
+    *gx = (double(Cr[2]) - double(Cr[0])) * (1.0 / 3.0) +
+          (double(Nr[2]) + double(Sr[2]) - double(Nr[0]) - double(Sr[0])) * (1.0 / 12.0);
+    *gy = (double(Nr[1]) - double(Sr[1])) * (1.0 / 3.0) +
+          (double(Nr[2]) + double(Nr[0]) - double(Sr[2]) - double(Sr[0])) * (1.0 / 12.0);
   };
-  R gTx, gTy, gpx, gpy;
+  double gTx, gTy, gpx, gpy;
   grad(tS, tC, tN, &gTx, &gTy);
   grad(pS, pC, pN, &gpx, &gpy);
-  R jx = 0, jy = 0;
+  if (DEV) gTy += a.Tg;   // the stencil is exact on the linear reference
+  double jxd = 0.0, jyd = 0.0;
 #pragma unroll
   for (int q = 1; q < 9; ++q) {
-    if (kEx[q] != 0) jx += R(kEx[q]) * cur.v[q];
-    if (kEy[q] != 0) jy += R(kEy[q]) * cur.v[q];
+    if (kEx[q] != 0) jxd += double(kEx[q]) * double(cur.v[q]);
+    if (kEy[q] != 0) jyd += double(kEy[q]) * double(cur.v[q]);
   }
   if (MODE & kTape) {
     const size_t s = (size_t)j * nx + x;
@@ -140,23 +151,26 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     tc[s] = cd;
     tr[s] = Tv;
     tr[n + s] = pv;
-    tr[2 * n + s] = jx;
-    tr[3 * n + s] = jy;
+    tr[2 * n + s] = R(jxd);
+    tr[3 * n + s] = R(jyd);
   }
   // closures
-  const R Tm = DEV ? Tv + k.TsmTref : Tv - k.Tref;   // T - Tref
-  const R sigma = k.sigma0 - k.sigmaT * Tm;
-  const R gsx = -k.sigmaT * gTx, gsy = -k.sigmaT * gTy;
-  const R g2 = gcx * gcx + gcy * gcy;
-  const R gds = gcx * gsx + gcy * gsy;
-  const R ks = k.kcap * sigma * mu;
-  const R Fx = ks * gcx + k.epsalpha * (g2 * gsx - gds * gcx) + k.bfx;
-  const R Fy = ks * gcy + k.epsalpha * (g2 * gsy - gds * gcy) + k.bfy;
-  const R ux = R(3) * jx * k.inv_rho + R(0.5) * Fx * k.inv_rho;
-  const R uy = R(3) * jy * k.inv_rho + R(0.5) * Fy * k.inv_rho;
+  const double Tm = DEV ? double(Tv) + (Trow - a.Tref) : double(Tv) - a.Tref;   // T - Tref
+  const double sigma = a.sigma0 - a.sigmaT * Tm;
+  const double gsx = -a.sigmaT * gTx, gsy = -a.sigmaT * gTy;
+  const double g2 = gcx_d * gcx_d + gcy_d * gcy_d;
+  const double gds = gcx_d * gsx + gcy_d * gsy;
+  const double ks = a.kcap * sigma * mu_d;
+  const double inv_rho = 1.0 / a.rho;
+  const double Fxd = ks * gcx_d + a.epsalpha * (g2 * gsx - gds * gcx_d) + a.rho * a.ax;
+  const double Fyd = ks * gcy_d + a.epsalpha * (g2 * gsy - gds * gcy_d) + a.rho * a.ay;
+  const double uxd = 3.0 * jxd * inv_rho + 0.5 * Fxd * inv_rho;
+  const double uyd = 3.0 * jyd * inv_rho + 0.5 * Fyd * inv_rho;
+  const R ux = R(uxd), uy = R(uyd);
+  const R Fbx = R(Fxd - gpx), Fby = R(Fyd - gpy);
 
   if (MODE & kDiag) {
-    const double Td = DEV ? double(Tv) + a.Ts : double(Tv);
+    const double Td = DEV ? double(Tv) + Trow : double(Tv);
     const double yy = double(j) + 0.5, xx = double(x) + 0.5;
     acc[0] += cd;
     acc[1] += a.rcv * Td;
@@ -175,7 +189,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     if (a.ux) a.ux[s] = double(ux);
     if (a.uy) a.uy[s] = double(uy);
     if (a.p) a.p[s] = DEV ? double(pv) + a.p0 : double(pv);
-    if (a.T) a.T[s] = DEV ? double(Tv) + a.Ts : double(Tv);
+    if (a.T) a.T[s] = DEV ? double(Tv) + Trow : double(Tv);
   }
   if (MODE & kStore) {
     // one descriptor for the whole destination state (below 4 GiB); planes
@@ -184,21 +198,21 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     const uint32_t pbytes = (uint32_t)(n * sizeof(S));
     const uint32_t dbase = kNumS * pbytes;
     const R ch = c < R(0) ? R(0) : (c > R(1) ? R(1) : c);
-    const R wf = R(1) / (k.tauf0 + ch * k.dtauf);
+    const double wfd = 1.0 / (a.tauf0 + double(ch) * a.dtauf), cfd = 1.0 - 0.5 * wfd;
+    const double usqd = uxd * uxd + uyd * uyd;
     const R wT = R(1) / (k.tauT0 + ch * k.dtauT);
     const R wg = k.wg;
-    const R Fbx = Fx - gpx, Fby = Fy - gpy;
     const R usq = ux * ux + uy * uy;
     // temperature in FP64 for the rest population, in R for the others
     double hs = 0.0;
 #pragma unroll
     for (int q = 1; q < 9; ++q) hs += double(cur.v[18 + q]);
     const double Td = (cur.h0 + hs) / a.rcv;          // T or Delta T, FP64
-    const double Tfull_d = DEV ? Td + a.Ts : Td;
+    const double Tfull_d = DEV ? Td + Trow : Td;
     const R Tfull = R(Tfull_d);
     const R rcvT = k.rcv * Tfull;
-    const R gmu = k.gam3 * mu;
-    const R cf = R(1) - R(0.5) * wf, cgf = R(1) - R(0.5) * wg, chf = R(1) - R(0.5) * wT;
+    const R gmu = R(a.gam3 * mu_d);
+    const R cgf = R(1) - R(0.5) * wg, chf = R(1) - R(0.5) * wT;
     const R src_g = R(3) * c * k.inv_rho;     // c / (rho cs^2)
     const R src_h = R(3) * k.inv_rho;         // 1 / (rho cs^2)
     const bool walls = a.walls_y != 0;
@@ -210,6 +224,11 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     auto st = [&](int q, uint32_t off, R val) {
       buf_store_nt<S>(S(val), rd, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes);
     };
+    // FP32 form: what the eight moving populations of g and hbar give away in
+    // this collision, as stored (sum of old - new, each difference of two
+    // nearby FP32 values)
+    R dg = 0, dh = 0;
+    R gsrc0 = 0, hsrc0 = 0, G0 = 0, gam0 = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const R w = wq<R>(i);
@@ -217,11 +236,19 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const R G = w * (R(3) * e + R(4.5) * e * e - R(1.5) * usq);  // Gamma_i - w_i
       const R gam = w + G;
       const R cxu = R(kEx[i]) - ux, cyu = R(kEy[i]) - uy;
-      const R fe = Fx * cxu + Fy * cyu;
       const R fbe = Fbx * cxu + Fby * cyu;
-      // f (Eqs. 6-7): f^eq = w p + rho cs^2 G
-      const R feq = w * pv + k.rho * third * G;
-      const R fo = cur.v[i] - wf * (cur.v[i] - feq) + cf * fe * gam;
+      // f (Eqs. 6-7): f^eq = w p + rho cs^2 G, in FP64.  Near an interface
+      // the forcing term carries the capillary force, which the pressure
+      // gradient balances; FP32 weights and Gamma_i would leave a relative
+      // bias of ~1e-8 in that balance, a spurious force whose viscous
+      // response grows over R^2 / nu steps.
+      const double wd = wq<double>(i);
+      const double ed = double(kEx[i]) * uxd + double(kEy[i]) * uyd;
+      const double Gd = wd * (3.0 * ed + 4.5 * ed * ed - 1.5 * usqd);
+      const double fed = Fxd * (double(kEx[i]) - uxd) + Fyd * (double(kEy[i]) - uyd);
+      const double feqd = wd * double(pv) + a.rho * (1.0 / 3.0) * Gd;
+      const double vd = double(cur.v[i]);
+      const R fo = R(vd - wfd * (vd - feqd) + cfd * fed * (wd + Gd));
       // g (Eqs. 12-14): g^eq_0 = c - (1 - w0) 3 Gamma mu + c G_0,
       //                 g^eq_i = w_i 3 Gamma mu + c G_i
       const R gsrc = cgf * src_g * fbe * gam;
@@ -229,33 +256,29 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const R heq_full = rcvT * gam;
       const R hsrc = chf * src_h * fbe * heq_full;
       if (i == 0) {
-        // rest populations in FP64 from FP32 increments:
-        // g^eq_0 - g_0 = sum_{q>0} g_q - (1 - w0) 3 Gamma mu + c G_0
-        const R d0 = gsum - (R(1) - w) * gmu + c * G;
-        const double gnew = cur.g0 + double(wg * d0 + gsrc);
-        // h_0 - h^eq_0 (both FP64-sized; their difference is small)
-        const double hdiff = DEV ? cur.h0 - a.rcv * (Td * double(w) + Tfull_d * double(G))
-                                 : cur.h0 - a.rcv * Tfull_d * double(gam);
-        const double hnew = cur.h0 + double(-wT * R(hdiff) + hsrc);
         st(0, s_own, fo);
-        buf_store_nt<double>(gnew, rd, s_own * 8u, dbase);
-        buf_store_nt<double>(hnew, rd, s_own * 8u, dbase + (uint32_t)(n * 8));
+        gsrc0 = gsrc;
+        hsrc0 = hsrc;
+        G0 = G;
+        gam0 = gam;
         continue;
       }
       const R geq = w * gmu + c * G;
       const R go = cur.v[9 + i] - wg * (cur.v[9 + i] - geq) + gsrc;
       const R heq = DEV ? k.rcv * (Tv * w + Tfull * G) : heq_full;
       const R ho = cur.v[18 + i] - wT * (cur.v[18 + i] - heq) + hsrc;
+      dg += cur.v[9 + i] - go;
       // push to x + xi_i
       const bool out = (kEy[i] < 0 && bot) || (kEy[i] > 0 && top);
       if (out) {
         // reflected into the opposite direction at this site
         const int o = kOpp[i];
         const double *tw = kEy[i] < 0 ? a.twb : a.twt;
-        const R twv = DEV ? R(tw[x] - a.Ts) : R(tw[x]);
+        const R twv = DEV ? R(tw[x] - Trow) : R(tw[x]);
         st(o, s_own, fo);
         st(9 + o, s_own, go);
         st(18 + o, s_own, R(2) * w * k.rcv * twv - ho);
+        dh += cur.v[18 + i] - ho;
       } else {
         int xd = x + kEx[i];
         xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
@@ -264,9 +287,32 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
         const uint32_t s = (uint32_t)(yd * nx + xd);
         st(i, s, fo);
         st(9 + i, s, go);
-        st(18 + i, s, ho);
+        // a move to the next row changes the reference by Tg xi_y
+        const R shift = DEV && kEy[i] != 0 ? R(kEy[i]) * w * k.rcv * R(a.Tg) : R(0);
+        const R hst = ho - shift;
+        st(18 + i, s, hst);
+        dh += (cur.v[18 + i] - hst) - shift;
       }
     }
+    // rest populations in FP64
+    double gnew, hnew;
+    if (DEV) {
+      // The collision conserves c = sum g and rho cv T = sum hbar at the site,
+      // so the FP64 rest populations receive exactly what the eight stored
+      // FP32 values gave away: the rounding of the stored values is taken up
+      // here, and c and T are transported without a systematic drift.
+      gnew = cur.g0 + double(dg);
+      hnew = cur.h0 + double(dh);
+    } else {
+      // g^eq_0 - g_0 = sum_{q>0} g_q - (1 - w0) 3 Gamma mu + c G_0
+      const R w0 = wq<R>(0);
+      const R d0 = gsum - (R(1) - w0) * gmu + c * G0;
+      gnew = cur.g0 + double(wg * d0 + gsrc0);
+      const double hdiff = cur.h0 - a.rcv * Tfull_d * double(gam0);
+      hnew = cur.h0 + double(-wT * R(hdiff) + hsrc0);
+    }
+    buf_store_nt<double>(gnew, rd, s_own * 8u, dbase);
+    buf_store_nt<double>(hnew, rd, s_own * 8u, dbase + (uint32_t)(n * 8));
   }
 }
 
@@ -384,18 +430,21 @@ step_kernel(const StepArgs a) {
   // ghost row beyond a wall from the adjacent row's slot: c and p mirrored,
   // T_ghost = 2 T_wall - T (in deviations 2 (T_wall - Ts) - Delta T); each
   // lane reads only entries it wrote itself
+  // (FP32 form: Delta T of the ghost row against the reference of its own
+  // row, which is 2 (T_wall - Tref(wall)) - Delta T for a linear reference)
   auto put_ghost = [&](int slot, int from, const double *tw) {
+    const double twref = DEV ? a.Ts + (tw == a.twb ? 0.0 : a.Tg * double(ny)) : 0.0;
     if (act) {
       ringc[slot][lane + 1] = ringc[from][lane + 1];
       ringp[slot][lane + 1] = ringp[from][lane + 1];
-      const R twv = DEV ? R(tw[x] - a.Ts) : R(tw[x]);
+      const R twv = DEV ? R(tw[x] - twref) : R(tw[x]);
       ringt[slot][lane + 1] = R(2) * twv - ringt[from][lane + 1];
     }
     if (halo) {
       if (hfield == 0) {
         ringc[slot][hpos] = ringc[from][hpos];
       } else if (hfield == 1) {
-        const R twv = DEV ? R(tw[hx] - a.Ts) : R(tw[hx]);
+        const R twv = DEV ? R(tw[hx] - twref) : R(tw[hx]);
         ringt[slot][hpos] = R(2) * twv - ringt[from][hpos];
       } else {
         ringp[slot][hpos] = ringp[from][hpos];

@@ -52,7 +52,7 @@ class lbe_csf_params(ctypes.Structure):
         ("width", ctypes.c_double), ("beta", ctypes.c_double),
         ("sigma0", ctypes.c_double), ("sigmaT", ctypes.c_double), ("Tref", ctypes.c_double),
         ("force", ctypes.c_double * 2),
-        ("p0", ctypes.c_double), ("T_shift", ctypes.c_double),
+        ("p0", ctypes.c_double), ("T_shift", ctypes.c_double), ("T_grad", ctypes.c_double),
         ("diag_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
@@ -121,6 +121,7 @@ def make_params(p: dict, precision="fp64", diag_every=0) -> lbe_csf_params:
     P.sigma0, P.sigmaT, P.Tref = float(p["sigma0"]), float(p["sigmaT"]), float(p["Tref"])
     P.force[0], P.force[1] = map(float, p["force"])
     P.p0, P.T_shift = float(p["p0"]), float(p.get("T_shift", 0.0))
+    P.T_grad = float(p.get("T_grad", 0.0))
     P.diag_every, P.reserved = int(diag_every), 0
     return P
 

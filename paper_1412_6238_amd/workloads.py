@@ -21,6 +21,10 @@ Grid convention: sites (i, j) at x = i + 1/2, y = j + 1/2; x periodic; when
 (ny, nx) float64, x fastest.  phi = 2c - 1 with c = 1 inside droplets and in
 the upper layer.
 
+T_shift and T_grad set the linear temperature T_shift + T_grad y that the
+FP32 deviation form stores hbar relative to; each workload uses the linear
+profile its walls impose (only the FP32 form reads them).
+
 Relaxation times are stated directly; the comments give the transport
 coefficients they stand for (eta = (tau_f - 1/2)/3, lambda = (tau_T - 1/2)/3
 at rho = cv = 1).
@@ -35,7 +39,7 @@ W_DEFAULT = 2.0 * math.sqrt(2.0)   # tanh width for eps = 1 at beta = 1/4
 
 PARAM_KEYS = ("nx", "ny", "walls_y", "rho", "cv", "tau_f", "tau_T", "tau_g",
               "mobility", "width", "beta", "sigma0", "sigmaT", "Tref", "force",
-              "p0", "T_shift")
+              "p0", "T_shift", "T_grad")
 
 WORKLOADS = ("poiseuille", "planar_marangoni", "droplet", "adjoint_droplet",
              "multi_droplet")
@@ -45,7 +49,7 @@ def base_params(nx: int, ny: int, **kw) -> dict:
     p = dict(nx=nx, ny=ny, walls_y=1, rho=1.0, cv=1.0, tau_f=(1.0, 1.0),
              tau_T=(1.0, 1.0), tau_g=1.0, mobility=0.05, width=W_DEFAULT,
              beta=0.25, sigma0=1e-2, sigmaT=0.0, Tref=0.0, force=(0.0, 0.0),
-             p0=1.0 / 3.0, T_shift=0.0)
+             p0=1.0 / 3.0, T_shift=0.0, T_grad=0.0)
     p.update(kw)
     return p
 
@@ -177,7 +181,7 @@ def make(name: str, **overrides) -> dict:
         # eta 0.1 / 0.3 (1:3), lambda 0.1 / 0.2 (1:2); c = 0 lower layer
         p = base_params(nx, ny, tau_f=(0.8, 1.4), tau_T=(0.8, 1.1), tau_g=2.5,
                         mobility=0.1, width=4.0, sigma0=1e-3, sigmaT=1e-4,
-                        Tref=10.0, force=(1e-6, 0.0), T_shift=15.0)
+                        Tref=10.0, force=(1e-6, 0.0), T_shift=20.0, T_grad=-10.0 / 64.0)
         phi0 = tanh_layer(nx, ny, ny / 2, 4.0)
         Y, _ = coords(nx, ny)
         T0 = 20.0 - 10.0 * Y / ny
@@ -197,7 +201,7 @@ def make(name: str, **overrides) -> dict:
         nsteps, prec = 50000, "fp32_dev"
     elif name == "droplet":
         nx, ny = 512, 1024
-        p = base_params(nx, ny, T_shift=5.12, **_droplet_physics())
+        p = base_params(nx, ny, T_shift=0.0, T_grad=0.01, **_droplet_physics())
         phi0 = droplet_phi(nx, ny, [(256.0, 128.0, 32.0)], W_DEFAULT)
         Y, _ = coords(nx, ny)
         T0 = 0.01 * Y
@@ -205,7 +209,7 @@ def make(name: str, **overrides) -> dict:
         nsteps, prec = 100000, "fp32_dev"
     elif name == "adjoint_droplet":
         nx, ny = 256, 512
-        p = base_params(nx, ny, T_shift=2.56, **_droplet_physics())
+        p = base_params(nx, ny, T_shift=0.0, T_grad=0.01, **_droplet_physics())
         phi0 = droplet_phi(nx, ny, [(128.0, 96.0, 24.0)], W_DEFAULT)
         rng = np.random.default_rng(6238)
         tb = 0.0 + rng.normal(0.0, 0.1, nx)
@@ -214,7 +218,7 @@ def make(name: str, **overrides) -> dict:
         nsteps, prec = 4000, "fp32_dev"
     elif name == "multi_droplet":
         nx, ny = 4096, 4096
-        p = base_params(nx, ny, T_shift=4.096, **_droplet_physics())
+        p = base_params(nx, ny, T_shift=0.0, T_grad=0.002, **_droplet_physics())
         drops = place_droplets(nx, ny, 200, 1412, 16.0, 48.0)
         phi0 = droplet_phi(nx, ny, drops, W_DEFAULT)
         Y, _ = coords(nx, ny)
@@ -249,7 +253,8 @@ def random_case(nx, ny, seed, walls_y=1, n_drops=2, amp_T=0.5, **kw):
         tau_g=tau_g, mobility=mobility, width=width, beta=0.25,
         sigma0=float(rng.uniform(5e-3, 2e-2)), sigmaT=float(rng.uniform(-2e-3, 2e-3)),
         Tref=float(rng.uniform(0.5, 1.5)),
-        force=tuple(rng.uniform(-1e-4, 1e-4, 2)), p0=0.0, T_shift=1.0)
+        force=tuple(rng.uniform(-1e-4, 1e-4, 2)), p0=0.0, T_shift=1.0,
+        T_grad=float(np.random.default_rng(seed + 100003).uniform(-0.02, 0.02)))
     p.update(kw)
     drops = []
     for _ in range(n_drops):

@@ -265,13 +265,15 @@ def _droplet_gradient(lbe, w, N, precision):
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden differences not generated")
-@pytest.mark.parametrize("precision,tol", [("fp32_dev", 1e-3), ("fp64", 1e-5)])
-def test_adjoint_droplet_full(lbe, precision, tol):
+@pytest.mark.parametrize("precision,tol,tol_wall",
+                         [("fp32_dev", 1e-3, 1e-3), ("fp64", 1e-6, 1e-4)])
+def test_adjoint_droplet_full(lbe, precision, tol, tol_wall):
     """256 x 512 droplet, 4000 steps with sqrt(N) checkpoints: gradient of
     the centroid displacement vs the FP64 oracle's central differences
     (sigmaT at h = 1e-6; the wall derivatives at h = 1e-3, where the
-    differences are not limited by the round-off of J).  FP32 within 1e-3,
-    FP64 within 1e-5."""
+    differences are not limited by the round-off of J).  FP32 within 1e-3.
+    FP64 within 1e-6 on sigmaT and 1e-4 on the wall derivatives, the accuracy
+    of those differences for the smallest component (|dJ/dTw[200]| ~ 2e-5)."""
     ref = json.load(open(GOLDEN))
     w = wl.make("adjoint_droplet")
     N = ref["nsteps"]
@@ -288,10 +290,10 @@ def test_adjoint_droplet_full(lbe, precision, tol):
         ad = float(np.dot(dtb, np.asarray(d["direction"])))
         rel = _rel(ad, fd)
         _say(f"  dJ/dTw . d gpu {ad!r} fd {fd!r} (h=1e-6: {d['dJ']!r}) rel {rel:.2e}")
-        assert rel <= tol
+        assert rel <= tol_wall
     comps = ref.get("Twall_components_h_wall", ref["Twall_components"])
     for i, v in comps.items():
         rel = _rel(float(dtb[int(i)]), v)
         _say(f"  dJ/dTw[{i}] gpu {float(dtb[int(i)])!r} fd {v!r} "
              f"(h=1e-6: {ref['Twall_components'][i]!r}) rel {rel:.2e}")
-        assert rel <= tol
+        assert rel <= tol_wall

@@ -233,10 +233,13 @@ def test_backward_requires_record(lbe):
 # ---- FP32 deviation form --------------------------------------------------------
 @pytest.mark.parametrize("name,nsteps,tol", [("planar_marangoni", 50000, 1e-4),
                                              ("poiseuille", 20000, 1e-4),
-                                             ("droplet", 2000, 1e-4)])
+                                             ("droplet", 100000, 1e-4),
+                                             ("multi_droplet", 2000, 1e-4)])
 def test_fp32_dev_vs_fp64(lbe, name, nsteps, tol):
-    """FP32 deviation storage against the FP64 path after the stated steps:
-    relative L2 on phi, u and T within tol; mass drift reported."""
+    """FP32 deviation storage against the FP64 path after the stated steps
+    (the FP64 path matches the oracle to 1e-12): relative L2 on phi, u and T
+    within tol; mass drift reported."""
+    import torch
     w = wl.make(name)
     _say(f"case fp32_dev vs fp64 {name} {nsteps}")
     res = {}
@@ -245,12 +248,15 @@ def test_fp32_dev_vs_fp64(lbe, name, nsteps, tol):
                              precision=prec)
         m0 = sim.diagnostics()["mass"]
         sim.step(nsteps)
-        res[prec] = (_fields_np(sim), sim.diagnostics()["mass"] / m0 - 1)
+        res[prec] = (sim.fields(), sim.diagnostics()["mass"] / m0 - 1)
+        del sim
     a, b = res["fp32_dev"][0], res["fp64"][0]
-    ua, ub = np.stack([a["ux"], a["uy"]]), np.stack([b["ux"], b["uy"]])
-    errs = {"phi": _rel(a["phi"], b["phi"]), "u": _rel(ua, ub), "T": _rel(a["T"], b["T"]),
-            "T-Tmin": _rel(a["T"] - b["T"].min(), b["T"] - b["T"].min())}
-    _say(f"  errors {errs}  mass drift fp64 {res['fp64'][1]:.2e} fp32 {res['fp32_dev'][1]:.2e}")
+    rel = lambda x, y: (torch.linalg.norm(x - y) / torch.linalg.norm(y)).item()
+    ua, ub = torch.stack([a["ux"], a["uy"]]), torch.stack([b["ux"], b["uy"]])
+    errs = {"phi": rel(a["phi"], b["phi"]), "u": rel(ua, ub), "T": rel(a["T"], b["T"]),
+            "T-Tmin": rel(a["T"] - b["T"].min(), b["T"] - b["T"].min())}
+    _say(f"  errors " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()) +
+         f"  mass drift fp64 {res['fp64'][1]:.2e} fp32 {res['fp32_dev'][1]:.2e}")
     for k in ("phi", "u", "T"):
         assert errs[k] <= tol, (k, errs[k])
 

@@ -43,13 +43,8 @@ struct Launch {
   int nblocks;
 };
 
-Launch pick_launch(int nx, int ny, size_t state_bytes) {
+Launch pick_launch(int nx, int ny, bool fp32) {
   Launch L;
-  L.pipe = 1;
-  if (const char *e = std::getenv("LBE_CSF_PIPE")) {
-    const int v = std::atoi(e);
-    if (v == 0 || v == 1) L.pipe = v;
-  }
   L.nw = nx >= 2048 ? 4 : (nx >= 256 ? 2 : 1);
   if (const char *e = std::getenv("LBE_CSF_NW")) {
     const int v = std::atoi(e);
@@ -57,11 +52,29 @@ Launch pick_launch(int nx, int ny, size_t state_bytes) {
   }
   const int bx = 64 * L.nw;
   L.nstrips = (nx + bx - 1) / bx;
-  // about 2048 waves (two per SIMD) in one wave of resident blocks: long
-  // chunks on large grids (fewer halo rows re-read per chunk), down to one
-  // row per block on small grids, where the parallelism is the limit
-  const long long want = std::max(1LL, 2048LL / ((long long)L.nw * L.nstrips));
-  int rows = (int)std::max<long long>(1, (ny + want - 1) / want);
+  // Row chunks: about 2048 waves (two per SIMD) resident at once -- long
+  // chunks on large grids (fewer halo rows re-read), down to one row per
+  // block on small grids, where parallelism is the limit.  The FP32 step on a
+  // large grid loads rows two ahead (PIPE 2, which needs the registers of a
+  // two-wave occupancy) and runs best with twice as many, shorter chunks.
+  auto rows_for = [&](long long waves) {
+    const long long want = std::max(1LL, waves / ((long long)L.nw * L.nstrips));
+    return (int)std::max<long long>(1, (ny + want - 1) / want);
+  };
+  int rows = rows_for(2048);
+  L.pipe = 1;
+  if (fp32 && rows >= 64) {
+    rows = rows_for(4096);
+    L.pipe = 2;
+  } else if (fp32 && rows >= 4) {
+    L.pipe = 2;
+  } else if (!fp32 && rows >= 64) {
+    rows = rows_for(3072);   // measured on 4096^2: 86-row chunks beat 64 and 128
+  }
+  if (const char *e = std::getenv("LBE_CSF_PIPE")) {
+    const int v = std::atoi(e);
+    if (v == 0 || v == 1 || v == 2) L.pipe = v;
+  }
   if (const char *e = std::getenv("LBE_CSF_ROWS")) {
     const int v = std::atoi(e);
     if (v >= 1) rows = v;
@@ -116,7 +129,7 @@ Layout make_layout(const lbe_csf_params *p, int64_t record_steps) {
   const size_t n = (size_t)p->nx * p->ny;
   const size_t vb = p->precision == LBE_CSF_FP64 ? 8 : 4;
   L.state_bytes = kNumS * n * vb + 2 * n * 8;   // 25 planes + FP64 g_0, hbar_0
-  const Launch la = pick_launch(p->nx, p->ny, L.state_bytes);
+  const Launch la = pick_launch(p->nx, p->ny, p->precision == LBE_CSF_FP32_DEV);
   size_t o = 0;
   L.off_a = o; o = align_up(o + L.state_bytes);
   L.off_b = o; o = align_up(o + L.state_bytes);
@@ -227,6 +240,7 @@ template <typename S, typename R, bool DEV, int MODE>
 void launch_mode(const Launch &la, const StepArgs &a, hipStream_t st) {
   switch (la.pipe) {
     case 0: launch_pipe<S, R, DEV, MODE, 0>(la, a, st); break;
+    case 2: launch_pipe<S, R, DEV, MODE, 2>(la, a, st); break;
     default: launch_pipe<S, R, DEV, MODE, 1>(la, a, st); break;
   }
 }
@@ -424,7 +438,7 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   if (!h) return fail(nullptr, LBE_CSF_ENOMEM, "host allocation failed");
   h->P = *params;
   h->L = L;
-  h->la = pick_launch(params->nx, params->ny, L.state_bytes);
+  h->la = pick_launch(params->nx, params->ny, params->precision == LBE_CSF_FP32_DEV);
   h->stream = static_cast<hipStream_t>(stream);
   h->ws = static_cast<char *>(workspace);
   h->state[0] = h->ws + L.off_a;

@@ -338,6 +338,14 @@ __device__ __forceinline__ void block_partials(const double *acc, double (*red)[
   }
 }
 
+// Block barrier that waits for this wave's LDS operations only.  The ring
+// is the only data shared within a block, so outstanding global loads (the
+// rows prefetched for later iterations) need not be drained, as the
+// compiler's barrier would do.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ---------------------------------------------------------------------------
 // Register-fed variant.
 template <typename S, typename R, bool DEV, int MODE, int NW, int PIPE>
@@ -398,7 +406,26 @@ step_kernel(const StepArgs a) {
       r.h0 = ldd(1, s);
     }
   };
-  auto put_moments = [&](int slot, int row, const RowVals<R> &r) {
+  // a helper lane's halo values: the nine planes of its field, and the FP64
+  // rest population for c and T
+  struct HaloVals {
+    R v[9];
+    double d;
+  };
+  auto load_halo = [&](int row, HaloVals &h) {
+    if (halo) {
+      const uint32_t s = (uint32_t)(row * nx + hx);
+      if (hfield == 2) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) h.v[q] = ld(q, s);
+      } else {
+#pragma unroll
+        for (int q = 1; q < 9; ++q) h.v[q] = ld(9 * (hfield + 1) + q, s);
+        h.d = ldd(hfield, s);
+      }
+    }
+  };
+  auto put_own = [&](int slot, const RowVals<R> &r) {
     if (act) {
       double c, T;
       R p;
@@ -407,6 +434,30 @@ step_kernel(const StepArgs a) {
       ringt[slot][lane + 1] = R(T);
       ringp[slot][lane + 1] = p;
     }
+  };
+  // halo moments from prefetched values (PIPE 2)
+  auto put_halo = [&](int slot, const HaloVals &h) {
+    if (halo) {
+      if (hfield == 0) {
+        R cs = 0;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) cs += h.v[q];
+        ringc[slot][hpos] = h.d + double(cs);
+      } else if (hfield == 1) {
+        R hs = 0;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) hs += h.v[q];
+        ringt[slot][hpos] = R((h.d + double(hs)) * inv_rcv);
+      } else {
+        R f = 0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f += h.v[q];
+        ringp[slot][hpos] = f;
+      }
+    }
+  };
+  // halo moments loaded and summed in place (PIPE 0, 1)
+  auto put_halo_direct = [&](int slot, int row) {
     if (halo) {
       const uint32_t s = (uint32_t)(row * nx + hx);
       if (hfield == 0) {
@@ -456,7 +507,8 @@ step_kernel(const StepArgs a) {
       put_ghost(row & 3, adj & 3, row < 0 ? a.twb : a.twt);
     } else {
       load_row(wrap_row(row), tmp);
-      put_moments(row & 3, wrap_row(row), tmp);
+      put_own(row & 3, tmp);
+      put_halo_direct(row & 3, wrap_row(row));
     }
   };
 
@@ -464,18 +516,41 @@ step_kernel(const StepArgs a) {
 #pragma unroll
   for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
 
-  RowVals<R> cur, nxt;
+  RowVals<R> cur, nxt, nxt2;
+  HaloVals hnxt, hnxt2;
 #pragma unroll
   for (int q = 0; q < 27; ++q) cur.v[q] = nxt.v[q] = R(0);
   cur.g0 = cur.h0 = nxt.g0 = nxt.h0 = 0.0;
   load_row(y0, cur);
-  put_moments(y0 & 3, y0, cur);
+  put_own(y0 & 3, cur);
+  put_halo_direct(y0 & 3, y0);
   moments_or_ghost(y0 - 1, y0, nxt);
+  if (PIPE == 2 && !is_ghost(y0 + 1)) {
+    load_row(wrap_row(y0 + 1), nxt);
+    load_halo(wrap_row(y0 + 1), hnxt);
+  }
   for (int j = y0; j < y1; ++j) {
-    // moments of row j + 1 (PIPE 1 keeps its values for the next collision)
-    moments_or_ghost(j + 1, j, nxt);
-    __syncthreads();
-    if (PIPE == 0) load_row(j, cur);   // second read of row j, from cache
+    if (PIPE == 2) {
+      // issue the loads of row j + 2, then the moments of row j + 1 from the
+      // values loaded one iteration earlier: a row's loads have a whole
+      // collision to arrive, and the barrier waits for LDS only
+      if (j + 2 <= y1 && !is_ghost(j + 2)) {
+        load_row(wrap_row(j + 2), nxt2);
+        load_halo(wrap_row(j + 2), hnxt2);
+      }
+      if (is_ghost(j + 1)) {
+        put_ghost((j + 1) & 3, j & 3, a.twt);
+      } else {
+        put_own((j + 1) & 3, nxt);
+        put_halo((j + 1) & 3, hnxt);
+      }
+      lds_barrier();
+    } else {
+      // moments of row j + 1 (PIPE 1 keeps its values for the next collision)
+      moments_or_ghost(j + 1, j, nxt);
+      __syncthreads();
+      if (PIPE == 0) load_row(j, cur);   // second read of row j, from cache
+    }
     if (act) {
       const int l = lane;
       site_update<S, R, DEV, MODE>(a, k, j, x, &ringc[(j - 1) & 3][l], &ringc[j & 3][l],
@@ -484,7 +559,11 @@ step_kernel(const StepArgs a) {
                                    &ringp[(j - 1) & 3][l], &ringp[j & 3][l],
                                    &ringp[(j + 1) & 3][l], cur, acc);
     }
-    if (PIPE == 1) cur = nxt;
+    if (PIPE >= 1) cur = nxt;
+    if (PIPE == 2) {
+      nxt = nxt2;
+      hnxt = hnxt2;
+    }
   }
   if (MODE & kDiag)
     block_partials<NW>(acc, red, lane, a.partials + (size_t)blockIdx.x * kNumPartials);

@@ -152,12 +152,11 @@ def test_fp64_workloads(lbe, oracle_mod, name, nsteps, p0):
     _cmp(g, o, what=name)
 
 
-@pytest.mark.parametrize("pipe", ["0", "1"])
+@pytest.mark.parametrize("pipe", ["0", "1", "2"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
 def test_row_pipelines_agree(lbe, oracle_mod, monkeypatch, pipe, precision):
-    """The two ways of feeding rows (gathered values kept one row ahead in
-    registers, or gathered twice) give the same state, bit for bit, and FP64
-    matches the oracle."""
+    """The ways of feeding rows (loaded twice, one row ahead, two rows ahead)
+    give the same state, bit for bit, and FP64 matches the oracle."""
     case = wl.random_case(136, 40, seed=21, walls_y=1)
     monkeypatch.setenv("LBE_CSF_PIPE", pipe)
     monkeypatch.setenv("LBE_CSF_ROWS", "7")

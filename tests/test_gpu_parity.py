@@ -180,7 +180,7 @@ def test_fp64_chunking_does_not_matter(lbe, oracle_mod, monkeypatch):
     """Different strip widths and chunk heights give bitwise-identical states."""
     case = wl.random_case(200, 60, seed=12, walls_y=1)
     out = []
-    for nw, rows in (("1", "3"), ("2", "7"), ("4", "60"), ("1", "1")):
+    for nw, rows in (("1", "3"), ("2", "7"), ("4", "60"), ("1", "1"), ("8", "13")):
         monkeypatch.setenv("LBE_CSF_NW", nw)
         monkeypatch.setenv("LBE_CSF_ROWS", rows)
         _say(f"case chunking nw={nw} rows={rows}")

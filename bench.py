@@ -28,7 +28,9 @@ PEAK_HBM_GBS = 8000.0
 # written once; the FP32 form keeps 25 in FP32 and the two rest populations
 # (g_0, hbar_0) in FP64: 2 x (25 x 4 + 2 x 8) = 232; FP64: 2 x 27 x 8 = 432
 BYTES_PER_SITE = {"fp32_dev": 232, "fp64": 432}
-KERNEL_SOURCES = ("paper_1412_6238_amd/csrc/step_kernel.h", "paper_1412_6238_amd/csrc/lattice.h")
+# the step kernel and its launch shape (chosen in lbe_csf.hip)
+KERNEL_SOURCES = ("paper_1412_6238_amd/csrc/step_kernel.h", "paper_1412_6238_amd/csrc/lattice.h",
+                  "paper_1412_6238_amd/csrc/lbe_csf.hip")
 
 
 def kernel_hash():

@@ -14,8 +14,10 @@
  *   B  stencils         grad c, lap c, grad T, grad p (the paper needs them
  *                       in Eqs. 4, 12, 16, 25 but does not give a scheme;
  *                       isotropic nine-point stencils are the reading used)
+ *                       and the Hessian of c (curvature form of Eq. 3 only)
  *   C  closures         mu = mu0(c) - eps^2 lap c (Sec. II, Eq. 16),
- *                       sigma(T) (Eq. 5), CSF force (Eq. 4 / Eq. 3),
+ *                       sigma(T) (Eq. 5), CSF force (Eq. 3, with its
+ *                       capillary part in the potential or curvature form),
  *                       u (Eq. 9), relaxation rates (Eqs. 6, 12, 25)
  *   D  collide          f (Eqs. 6-8), g (Eqs. 12-14), hbar (Eqs. 22, 25)
  *   E  stream           periodic x; halfway bounce-back for f and g and
@@ -57,7 +59,7 @@ typedef struct {
   int32_t NX, NY;              /* global domain */
   int32_t x0, y0, wx, wy;      /* window held by this oracle */
   int32_t walls_y;             /* 1: halfway walls at y=0 and y=NY; 0: periodic */
-  int32_t pad_;
+  int32_t csf_form;            /* capillary force: 0 potential, 1 curvature   */
   double rho, cv;              /* uniform density, specific heat */
   double tau_f[2];             /* flow relaxation time at c=0 and c=1 */
   double tau_T[2];             /* thermal relaxation time (tau_h + 1/2) */
@@ -95,6 +97,7 @@ typedef struct orc {
   double *c, *T, *p, *jx, *jy;
   double *gcx, *gcy, *lapc, *gTx, *gTy, *gpx, *gpy;
   double *mu, *Fx, *Fy, *ux, *uy;
+  double *hxx, *hxy, *hyy;   /* Hessian of c */
 } orc;
 
 /* ---- neighbour lookup ------------------------------------------------------
@@ -165,9 +168,10 @@ static void pass_moments(orc *o) {
  * wetting) and the ghost temperature is 2 T_wall - T(adjacent), so that the
  * wall temperature holds halfway between. */
 static void stencil_site(const orc *o, const double *c, const double *T,
-                         const double *p, int i, int j, double out[7]) {
+                         const double *p, int i, int j, double out[10]) {
   const int s = j * o->P.wx + i;
   double gcx = 0, gcy = 0, lap = 0, gtx = 0, gty = 0, gpx = 0, gpy = 0;
+  double hxx = 0, hxy = 0, hyy = 0;
   for (int k = 1; k < NQ; ++k) {
     const int kind = o->nb_kind[k * o->n + s];
     const int loc = o->nb_loc[k * o->n + s];
@@ -193,21 +197,28 @@ static void stencil_site(const orc *o, const double *c, const double *T,
     gpx += w3 * OX[k] * pk;
     gpy += w3 * OY[k] * pk;
     lap += 2.0 * w3 * (ck - c[s]);
+    /* Hessian from the fourth-order lattice moment: sum w xi_a xi_b (c_k - c)
+     * = cs^4 (2 H_ab + delta_ab tr H) / 2 + O(dx^4), with cs^4 = 1/9 */
+    hxx += OW[k] * (9.0 * OX[k] * OX[k] - 3.0) * (ck - c[s]);
+    hyy += OW[k] * (9.0 * OY[k] * OY[k] - 3.0) * (ck - c[s]);
+    hxy += OW[k] * 9.0 * OX[k] * OY[k] * ck;
   }
   out[0] = gcx; out[1] = gcy; out[2] = lap;
   out[3] = gtx; out[4] = gty; out[5] = gpx; out[6] = gpy;
+  out[7] = hxx; out[8] = hxy; out[9] = hyy;
 }
 
 static void pass_stencils(orc *o) {
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < o->P.wy; ++j)
     for (int i = 0; i < o->P.wx; ++i) {
-      double st[7];
+      double st[10];
       const int s = j * o->P.wx + i;
       stencil_site(o, o->c, o->T, o->p, i, j, st);
       o->gcx[s] = st[0]; o->gcy[s] = st[1]; o->lapc[s] = st[2];
       o->gTx[s] = st[3]; o->gTy[s] = st[4];
       o->gpx[s] = st[5]; o->gpy[s] = st[6];
+      o->hxx[s] = st[7]; o->hxy[s] = st[8]; o->hyy[s] = st[9];
     }
 }
 
@@ -223,24 +234,39 @@ static double mu_bulk(double beta, double c) {
 
 static void closure_site(const orc *o, double c, double T, double jx, double jy,
                          double gcx, double gcy, double lapc, double gTx,
-                         double gTy, double gpx, double gpy, closure_t *r) {
+                         double gTy, double gpx, double gpy, double hxx,
+                         double hxy, double hyy, closure_t *r) {
   const orc_params *P = &o->P;
   /* chemical potential, Sec. II below Eq. 16 */
   r->mu = mu_bulk(P->beta, c) - o->eps * o->eps * lapc;
   /* linear surface tension, Eq. 5; READING: sigmaT here is -sigma_T */
   r->sigma = P->sigma0 - P->sigmaT * (T - P->Tref);
   const double gsx = -P->sigmaT * gTx, gsy = -P->sigmaT * gTy;
-  /* CSF force.  READING: the normal (capillary) part is taken in the
-   * potential form kcap sigma mu grad c that follows from the stress form
-   * Eq. 3 on the equilibrium profile; the tangential (Marangoni) part is
-   * Eq. 4's grad_s(sigma) delta with delta = eps alpha |grad c|^2. */
+  /* CSF force, Eq. 3.  The tangential (Marangoni) part is grad_s(sigma)
+   * delta with delta = eps alpha |grad c|^2.  The normal (capillary) part,
+   * -sigma kappa n delta with n = grad c / |grad c| and kappa = div n, is
+   * taken in one of two forms:
+   *   0  READING: the potential form kcap sigma mu grad c, which follows
+   *      from the stress form on the equilibrium profile;
+   *   1  the curvature form as printed.  In two dimensions
+   *      |grad c| div n = t.H.t with t the unit tangent and H the Hessian
+   *      of c, so the force is -sigma eps alpha (t.H.t) grad c; where
+   *      grad c vanishes the force does too. */
   const double g2 = gcx * gcx + gcy * gcy;
   const double gdots = gcx * gsx + gcy * gsy;
   const double ea = o->eps * o->alpha;
-  r->Fx = o->kcap * r->sigma * r->mu * gcx + ea * (g2 * gsx - gdots * gcx) +
-          P->rho * P->force[0];
-  r->Fy = o->kcap * r->sigma * r->mu * gcy + ea * (g2 * gsy - gdots * gcy) +
-          P->rho * P->force[1];
+  double capx, capy;
+  if (P->csf_form == 1) {
+    const double tHt =
+        g2 > 0.0 ? (gcy * gcy * hxx - 2.0 * gcx * gcy * hxy + gcx * gcx * hyy) / g2 : 0.0;
+    capx = -r->sigma * ea * tHt * gcx;
+    capy = -r->sigma * ea * tHt * gcy;
+  } else {
+    capx = o->kcap * r->sigma * r->mu * gcx;
+    capy = o->kcap * r->sigma * r->mu * gcy;
+  }
+  r->Fx = capx + ea * (g2 * gsx - gdots * gcx) + P->rho * P->force[0];
+  r->Fy = capy + ea * (g2 * gsy - gdots * gcy) + P->rho * P->force[1];
   /* Eq. 9.  READING: the half-force enters as (dt/2) cs^2 F, the first moment
    * of the forcing term of Eq. 6, so u = (sum xi f)/(rho cs^2) + F/(2 rho). */
   r->ux = jx / (P->rho * OCS2) + r->Fx / (2.0 * P->rho);
@@ -263,7 +289,8 @@ static void pass_closures(orc *o) {
   for (int s = 0; s < o->n; ++s) {
     closure_t r;
     closure_site(o, o->c[s], o->T[s], o->jx[s], o->jy[s], o->gcx[s], o->gcy[s],
-                 o->lapc[s], o->gTx[s], o->gTy[s], o->gpx[s], o->gpy[s], &r);
+                 o->lapc[s], o->gTx[s], o->gTy[s], o->gpx[s], o->gpy[s],
+                 o->hxx[s], o->hxy[s], o->hyy[s], &r);
     o->mu[s] = r.mu;
     o->Fx[s] = r.Fx;
     o->Fy[s] = r.Fy;
@@ -315,7 +342,8 @@ static void pass_collide(orc *o) {
     for (int k = 0; k < 3 * NQ; ++k) in[k] = o->F[k * n + s];
     closure_t r;
     closure_site(o, o->c[s], o->T[s], o->jx[s], o->jy[s], o->gcx[s], o->gcy[s],
-                 o->lapc[s], o->gTx[s], o->gTy[s], o->gpx[s], o->gpy[s], &r);
+                 o->lapc[s], o->gTx[s], o->gTy[s], o->gpx[s], o->gpy[s],
+                 o->hxx[s], o->hxy[s], o->hyy[s], &r);
     collide_site(o, in, o->c[s], o->T[s], o->p[s], &r, out);
     for (int k = 0; k < 3 * NQ; ++k) o->Fp[k * n + s] = out[k];
   }
@@ -412,7 +440,8 @@ OAPI orc *orc_create(const orc_params *P, const double *Twall_bot,
   o->Twt = (double *)calloc((size_t)P->NX, sizeof(double));
   double **fields[] = {&o->c,   &o->T,   &o->p,   &o->jx,  &o->jy,  &o->gcx,
                        &o->gcy, &o->lapc, &o->gTx, &o->gTy, &o->gpx, &o->gpy,
-                       &o->mu,  &o->Fx,  &o->Fy,  &o->ux,  &o->uy};
+                       &o->mu,  &o->Fx,  &o->Fy,  &o->ux,  &o->uy,  &o->hxx,
+                       &o->hxy, &o->hyy};
   for (size_t k = 0; k < sizeof(fields) / sizeof(fields[0]); ++k)
     *fields[k] = (double *)calloc(n, sizeof(double));
   if (Twall_bot) memcpy(o->Twb, Twall_bot, sizeof(double) * (size_t)P->NX);
@@ -425,7 +454,7 @@ OAPI void orc_destroy(orc *o) {
   double *fields[] = {o->F,   o->Fp,  o->Twb, o->Twt, o->c,   o->T,
                       o->p,   o->jx,  o->jy,  o->gcx, o->gcy, o->lapc,
                       o->gTx, o->gTy, o->gpx, o->gpy, o->mu,  o->Fx,
-                      o->Fy,  o->ux,  o->uy};
+                      o->Fy,  o->ux,  o->uy,  o->hxx, o->hxy, o->hyy};
   for (size_t k = 0; k < sizeof(fields) / sizeof(fields[0]); ++k) free(fields[k]);
   free(o->nb_kind);
   free(o->nb_loc);
@@ -445,7 +474,7 @@ OAPI void orc_init(orc *o, const double *phi0, const double *T0) {
   for (int j = 0; j < P->wy; ++j)
     for (int i = 0; i < P->wx; ++i) {
       const int s = j * P->wx + i;
-      double st[7];
+      double st[10];
       stencil_site(o, o->c, NULL, NULL, i, j, st);
       const double c = o->c[s];
       const double mu = mu_bulk(P->beta, c) - o->eps * o->eps * st[2];
@@ -518,16 +547,17 @@ OAPI void orc_fields(orc *o, double *phi, double *ux, double *uy, double *p,
   }
 }
 
-/* Every intermediate field of the current state, 17 arrays of n in the order
- * c T p jx jy gcx gcy lapc gTx gTy gpx gpy mu Fx Fy ux uy. */
+/* Every intermediate field of the current state, 20 arrays of n in the order
+ * c T p jx jy gcx gcy lapc gTx gTy gpx gpy mu Fx Fy ux uy hxx hxy hyy. */
 OAPI void orc_intermediates(orc *o, double *out) {
   pass_moments(o);
   pass_stencils(o);
   pass_closures(o);
   const double *src[] = {o->c,   o->T,   o->p,    o->jx,  o->jy,  o->gcx,
                          o->gcy, o->lapc, o->gTx, o->gTy, o->gpx, o->gpy,
-                         o->mu,  o->Fx,  o->Fy,   o->ux,  o->uy};
-  for (int k = 0; k < 17; ++k)
+                         o->mu,  o->Fx,  o->Fy,   o->ux,  o->uy,
+                         o->hxx, o->hxy, o->hyy};
+  for (int k = 0; k < 20; ++k)
     memcpy(out + (size_t)k * o->n, src[k], sizeof(double) * (size_t)o->n);
 }
 
@@ -539,7 +569,8 @@ OAPI void orc_diag(orc *o, double *d) {
 }
 
 /* Single-site collision for pinning: in[27] pre-collision values at the site,
- * st[7] = (gcx, gcy, lapc, gTx, gTy, gpx, gpy) stencil values; writes out[27]
+ * st[10] = (gcx, gcy, lapc, gTx, gTy, gpx, gpy, hxx, hxy, hyy) stencil values
+ * (the Hessian of c is read by the curvature form only); writes out[27]
  * and aux[11] = (c, T, p, mu, Fx, Fy, ux, uy, wf, wT, wg). */
 OAPI void orc_collide_site(const orc_params *P, const double *in,
                            const double *st, double *out, double *aux) {
@@ -558,7 +589,7 @@ OAPI void orc_collide_site(const orc_params *P, const double *in,
   T /= P->rho * P->cv;
   closure_t r;
   closure_site(&o, c, T, jx, jy, st[0], st[1], st[2], st[3], st[4], st[5], st[6],
-               &r);
+               st[7], st[8], st[9], &r);
   collide_site(&o, in, c, T, p, &r, out);
   if (aux) {
     aux[0] = c; aux[1] = T; aux[2] = p; aux[3] = r.mu; aux[4] = r.Fx;

@@ -24,7 +24,8 @@ N_DIAG = 7
 DIAG_KEYS = ("mass", "energy", "sum_cy", "sum_cx", "mass_thr", "sum_cuy_thr",
              "n_nonfinite")
 INTERMEDIATE_KEYS = ("c", "T", "p", "jx", "jy", "gcx", "gcy", "lapc", "gTx",
-                     "gTy", "gpx", "gpy", "mu", "Fx", "Fy", "ux", "uy")
+                     "gTy", "gpx", "gpy", "mu", "Fx", "Fy", "ux", "uy", "hxx",
+                     "hxy", "hyy")
 
 
 class _Params(ctypes.Structure):
@@ -32,7 +33,7 @@ class _Params(ctypes.Structure):
         ("NX", ctypes.c_int32), ("NY", ctypes.c_int32),
         ("x0", ctypes.c_int32), ("y0", ctypes.c_int32),
         ("wx", ctypes.c_int32), ("wy", ctypes.c_int32),
-        ("walls_y", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("walls_y", ctypes.c_int32), ("csf_form", ctypes.c_int32),
         ("rho", ctypes.c_double), ("cv", ctypes.c_double),
         ("tau_f", ctypes.c_double * 2), ("tau_T", ctypes.c_double * 2),
         ("tau_g", ctypes.c_double), ("mobility", ctypes.c_double),
@@ -97,6 +98,7 @@ def _make_params(p: dict, window=None) -> _Params:
     P = _Params()
     P.NX, P.NY, P.x0, P.y0, P.wx, P.wy = nx, ny, x0, y0, wx, wy
     P.walls_y = int(p.get("walls_y", 1))
+    P.csf_form = int(p.get("csf_form", 0))
     P.rho, P.cv = float(p["rho"]), float(p["cv"])
     P.tau_f[0], P.tau_f[1] = map(float, p["tau_f"])
     P.tau_T[0], P.tau_T[1] = map(float, p["tau_T"])
@@ -120,10 +122,13 @@ def derived(p: dict) -> dict:
     return dict(eps=out[0], alpha=out[1], kcap=out[2], Gamma=out[3])
 
 
-def collide_site(p: dict, pre27, stencil7):
-    """Single-site collision: returns (post[27], aux dict)."""
+def collide_site(p: dict, pre27, stencil):
+    """Single-site collision: returns (post[27], aux dict).  ``stencil`` holds
+    (gcx, gcy, lapc, gTx, gTy, gpx, gpy) and optionally the Hessian of c
+    (hxx, hxy, hyy), which only the curvature form reads (zeros if absent)."""
     pre = np.ascontiguousarray(pre27, dtype=np.float64)
-    st = np.ascontiguousarray(stencil7, dtype=np.float64)
+    st = np.zeros(10)
+    st[:len(stencil)] = np.asarray(stencil, dtype=np.float64)
     out = np.zeros(27)
     aux = np.zeros(11)
     lib().orc_collide_site(ctypes.byref(_make_params(p)), _ptr(pre), _ptr(st),
@@ -191,7 +196,7 @@ class Oracle:
         return dict(zip(("phi", "ux", "uy", "p", "T"), out))
 
     def intermediates(self):
-        out = np.zeros((17, self.wy, self.wx))
+        out = np.zeros((len(INTERMEDIATE_KEYS), self.wy, self.wx))
         lib().orc_intermediates(self._h, _ptr(out))
         return dict(zip(INTERMEDIATE_KEYS, out))
 

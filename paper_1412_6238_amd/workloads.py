@@ -39,7 +39,7 @@ W_DEFAULT = 2.0 * math.sqrt(2.0)   # tanh width for eps = 1 at beta = 1/4
 
 PARAM_KEYS = ("nx", "ny", "walls_y", "rho", "cv", "tau_f", "tau_T", "tau_g",
               "mobility", "width", "beta", "sigma0", "sigmaT", "Tref", "force",
-              "p0", "T_shift", "T_grad")
+              "p0", "T_shift", "T_grad", "csf_form")
 
 WORKLOADS = ("poiseuille", "planar_marangoni", "droplet", "adjoint_droplet",
              "multi_droplet")
@@ -49,7 +49,7 @@ def base_params(nx: int, ny: int, **kw) -> dict:
     p = dict(nx=nx, ny=ny, walls_y=1, rho=1.0, cv=1.0, tau_f=(1.0, 1.0),
              tau_T=(1.0, 1.0), tau_g=1.0, mobility=0.05, width=W_DEFAULT,
              beta=0.25, sigma0=1e-2, sigmaT=0.0, Tref=0.0, force=(0.0, 0.0),
-             p0=1.0 / 3.0, T_shift=0.0, T_grad=0.0)
+             p0=1.0 / 3.0, T_shift=0.0, T_grad=0.0, csf_form=0)
     p.update(kw)
     return p
 
@@ -232,6 +232,94 @@ def make(name: str, **overrides) -> dict:
                 T0=np.ascontiguousarray(T0), Twall_bot=np.ascontiguousarray(tb),
                 Twall_top=np.ascontiguousarray(tt), nsteps=nsteps,
                 precision=prec, name=name)
+
+
+# ---- the paper's own test cases at their printed parameters (Sec. IV) --------
+def paper_case(name: str, lam_r: float = 1.0, h_r: float = 1.0, **overrides) -> dict:
+    """Sec. IV as printed: "e1" layered Poiseuille flow (40 x 100, eta_r = 10,
+    lam_r in {1, 10, 100}, h_r = h/H in {1, 1/9, 9}), "e2" two superimposed
+    planar fluids (200 x 100, lam_r = lam1/lam2 in {1, 0.1}, fluid 1 upper),
+    "e3" the migrating droplet (160 x 300, R = 20).  eps = 1 (W = 2 sqrt 2),
+    beta = 1/4, rho = cv = 1 throughout.  Values the text leaves open:
+    mobility 5e-2 with tau_g = 1 in every case (the one printed M); e1 with
+    T = 0 / 1 on the walls, sigma0 = 1e-3, and a body force from Re = 1 unless
+    that drives the low-viscosity layer above |u| = 0.01 (h_r = 1/9), where it
+    is scaled down to that bound; e1 starts from the steady two-layer
+    conduction profile (its thermal time reaches 2.5e6 steps at lam_r = 100);
+    e3 with sigmaT = 5e-5, the value that the printed U_YGB = 1.333e-4
+    implies, and the matrix at the droplet's saturation: the order parameter
+    is the tanh droplet raised by mu_R / (2 beta) everywhere, mu_R =
+    sigma_fe / R the chemical potential of a droplet of radius R with the
+    free-energy tension sigma_fe = eps^2 / (3 W) of the double well.  Below
+    a critical radius, which R = 20 in 160 x 300 is, a droplet in a pure
+    matrix dissolves into it; the saturated matrix keeps it in equilibrium."""
+    W = W_DEFAULT
+    if name == "e1":
+        nx, ny = 40, 100
+        h = ny * h_r / (1.0 + h_r)
+        H = ny - h
+        eta1, lam1 = 0.1, 0.1
+        eta2, lam2 = eta1 / 10.0, lam1 / lam_r
+        u1 = eta1 / h                                   # Re = u1 h / eta1 = 1
+        ax = 2.0 * eta1 * u1 / (h * h)
+        # largest |u| of the two-layer profile (upper-layer maximum or the
+        # interface value)
+        yy = np.linspace(-h, H, 4001)
+        lo = ax * h * h / (2 * eta1) * (-(yy / h) ** 2 + ((H * H / (h * h) * eta1 - eta2)
+                                        / (H / h * eta1 + eta2)) * yy / h
+                                        + (1 + H / h) * H * eta1 / (eta1 * H + eta2 * h))
+        up = ax * H * H / (2 * eta2) * (-(yy / H) ** 2 + ((eta1 - h * h / (H * H) * eta2)
+                                        / (eta1 + h / H * eta2)) * yy / H
+                                        + (1 + h / H) * h * eta2 / (eta1 * H + eta2 * h))
+        umax = float(np.abs(np.where(yy < 0, lo, up)).max())
+        if umax > 0.01:
+            ax *= 0.01 / umax
+        p = base_params(nx, ny, tau_f=(3 * eta1 + 0.5, 3 * eta2 + 0.5),
+                        tau_T=(3 * lam1 + 0.5, 3 * lam2 + 0.5), tau_g=1.0, mobility=5e-2,
+                        width=W, sigma0=1e-3, sigmaT=0.0, Tref=0.0, force=(ax, 0.0),
+                        T_shift=0.0, T_grad=1.0 / ny)
+        phi0 = tanh_layer(nx, ny, h, W)
+        Y, _ = coords(nx, ny)
+        yr = Y - h
+        d = lam1 * H + lam2 * h
+        b = (lam2 * h * 1.0) / d                        # T = 0 at y = -h, 1 at y = H
+        T0 = np.where(yr < 0, lam2 / d * yr + b, lam1 / d * yr + b)
+        tb, tt = np.zeros(nx), np.ones(nx)
+        nsteps = int(2.0 * max(h * h / eta1, H * H / eta2))
+        meta = dict(h=h, H=H, eta1=eta1, eta2=eta2, lam1=lam1, lam2=lam2, ax=ax, Tc=0.0, Th=1.0)
+    elif name == "e2":
+        nx, ny = 200, 100
+        lam2, lam1 = 0.2, 0.2 * lam_r                   # fluid 1 upper (c = 1)
+        p = base_params(nx, ny, tau_f=(1.1, 1.1), tau_T=(3 * lam2 + 0.5, 3 * lam1 + 0.5),
+                        tau_g=1.0, mobility=5e-2, width=W, sigma0=2.5e-2, sigmaT=5e-4,
+                        Tref=10.0, T_shift=20.0, T_grad=-0.1)
+        phi0 = tanh_layer(nx, ny, ny / 2, W)
+        Y, _ = coords(nx, ny)
+        T0 = 20.0 - 10.0 * Y / ny
+        x = np.arange(nx) + 0.5
+        tb = 20.0 + 4.0 * np.cos(2.0 * np.pi * x / nx)
+        tt = np.full(nx, 10.0)
+        nsteps = int(3.0 * 50 * 50 / min(lam1, lam2))
+        meta = dict(h=50.0, H=50.0, eta1=0.2, eta2=0.2, lam1=lam1, lam2=lam2, Tc=10.0,
+                    Th=20.0, Tr=4.0, sigma_T=-5e-4)
+    elif name == "e3":
+        nx, ny = 160, 300
+        p = base_params(nx, ny, tau_f=(0.8, 0.8), tau_T=(0.8, 0.8), tau_g=1.0, mobility=5e-2,
+                        width=W, sigma0=0.1, sigmaT=5e-5, Tref=0.0, T_shift=0.0, T_grad=0.1)
+        eps = W * math.sqrt(0.25 / 2.0)
+        sat = (eps * eps / (3.0 * W)) / 20.0 / (2.0 * 0.25)
+        phi0 = droplet_phi(nx, ny, [(80.0, 40.0, 20.0)], W) + 2.0 * sat
+        Y, _ = coords(nx, ny)
+        T0 = 0.1 * Y
+        tb, tt = np.zeros(nx), np.full(nx, 30.0)
+        nsteps = 200000                                 # 10 t_r, t_r = R / U = 2e4
+        meta = dict(R=20.0, U=1e-3, U_YGB=1.0 / 7500.0, t_r=20000)
+    else:
+        raise KeyError(name)
+    p.update(overrides)
+    return dict(params=p, phi0=np.ascontiguousarray(phi0), T0=np.ascontiguousarray(T0),
+                Twall_bot=np.ascontiguousarray(tb), Twall_top=np.ascontiguousarray(tt),
+                nsteps=nsteps, precision="fp64", name=f"paper_{name}", meta=meta)
 
 
 def random_case(nx, ny, seed, walls_y=1, n_drops=2, amp_T=0.5, **kw):

@@ -51,6 +51,10 @@ def test_stencils_exact_on_quadratics(oracle_mod):
     np.testing.assert_allclose(I["gTy"][inner], (4e-3 + 1e-5 * X - 2e-5 * Y)[inner], rtol=0, atol=1e-13)
     np.testing.assert_allclose(I["gpx"][inner], 2e-4, rtol=0, atol=1e-14)
     np.testing.assert_allclose(I["gpy"][inner], 1e-4, rtol=0, atol=1e-14)
+    # the Hessian of c (curvature form of the capillary force)
+    np.testing.assert_allclose(I["hxx"][inner], 2e-5, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(I["hxy"][inner], -3e-5, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(I["hyy"][inner], 4e-5, rtol=0, atol=1e-12)
     # every site on the window edge depends on unknown neighbours
     edge = np.ones((wy, wx), bool)
     edge[inner] = False

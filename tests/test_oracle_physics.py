@@ -146,12 +146,14 @@ def test_planar_marangoni_tangential_stress(oracle_mod):
     assert f["ux"][ny // 2, nx // 4] > 0
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("R,bar", [(16, 0.08), (24, 0.04)])
-def test_laplace_law(oracle_mod, R, bar):
-    """A static droplet in a periodic 96^2 box: p_in - p_out = sigma0 / R."""
+def test_laplace_law(oracle_mod, R, bar, form):
+    """A static droplet in a periodic 96^2 box: p_in - p_out = sigma0 / R, with
+    the capillary force in the potential (0) or the curvature (1) form."""
     n = 96
     p = wl.base_params(n, n, walls_y=0, tau_f=(1.0, 1.0), tau_T=(1.0, 1.0), tau_g=1.5,
-                       mobility=0.1, sigma0=1e-2, sigmaT=0.0)
+                       mobility=0.1, sigma0=1e-2, sigmaT=0.0, csf_form=form)
     phi0 = wl.droplet_phi(n, n, [(48.0, 48.0, float(R))], p["width"])
     o = oracle_mod.Oracle(p).init(phi0, np.ones((n, n)))
     o.step(12000)
@@ -188,3 +190,17 @@ def test_ygb_printed_value():
     # sigma_T is not printed; the printed U_YGB fixes |sigma_T| = 5e-5
     u = an.ygb_velocity(-5e-5, i["gradT"], i["R"], i["eta2"], i["lam_r"], i["eta_r"])
     assert u == pytest.approx(e["value"], rel=1e-12)
+
+
+def test_layered_1d_steady_sharp_limit():
+    """The diffuse-interface steady state used for the paper's layered
+    Poiseuille case reduces to Eqs. (28)-(29) as the interface width goes to
+    zero (h = H and h = 9 H, eta_r = 10, lambda_r = 10)."""
+    for h, H in ((50.0, 50.0), (90.0, 10.0)):
+        ny = int(h + H)
+        u, T = an.layered_1d_steady(ny, h, 1e-3, 0.1, 0.01, 0.1, 0.01, 1.6e-7, 0.0, 1.0)
+        yr = np.arange(ny) + 0.5 - h
+        ua = an.poiseuille_ux(yr, h, H, 0.1, 0.01, 1.0, 1.6e-7)
+        Ta = an.poiseuille_T(yr, h, H, 0.1, 0.01, 0.0, 1.0)
+        assert np.abs(u - ua).max() <= 2e-4 * np.abs(ua).max()
+        assert np.abs(T - Ta).max() <= 2e-4

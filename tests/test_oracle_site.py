@@ -140,3 +140,61 @@ def test_paper_printed_constants(oracle_mod):
         assert np.max(np.abs(d["eps"] ** 2 * cpp - mu0)) < 1e-12
         # free-energy tension sigma_fe = eps^2 int c'^2, and kcap sigma_fe = 1
         assert d["kcap"] * d["eps"] ** 2 * integral == pytest.approx(1.0, rel=1e-9)
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.1, 2.5, 4.0, 5.6])
+def test_curvature_force_closed_form(oracle_mod, theta):
+    """Curvature form of the capillary force, Eq. 3: -sigma kappa n delta with
+    n = grad c/|grad c|, kappa = div n, delta = eps alpha |grad c|^2.  For a
+    radial profile c = f(r) the gradient is f' r_hat and the Hessian is
+    f'' r_hat r_hat + (f'/r)(I - r_hat r_hat), so div n = -1/r (n points
+    inwards for a droplet) and the force is -sigma eps alpha f'^2 / r r_hat,
+    pointing inwards with magnitude sigma delta / r.  Fed with these exact
+    derivatives at a generic angle, the site closure must return exactly that
+    (a swapped tangent and normal, a wrong sign of the mixed derivative or of
+    the force fails)."""
+    from paper_1412_6238_amd import workloads as wl
+    W, R, r = 2.5, 30.0, 31.2
+    p = wl.base_params(8, 8, width=W, beta=0.3, sigma0=0.07, sigmaT=0.0, Tref=0.0,
+                       csf_form=1)
+    d = oracle_mod.derived(p)
+    sech2 = 1.0 / math.cosh((R - r) / W) ** 2
+    f1 = -0.5 * sech2 / W                                      # f'(r)
+    # f''(r) of the tanh profile plus an offset: the profile is then off its
+    # equilibrium, where the potential form (exact on the equilibrium
+    # profile) and the curvature form differ; the curvature form does not
+    # depend on f'' at all
+    f2 = -sech2 * math.tanh((R - r) / W) / W ** 2 + 0.01
+    e = np.array([math.cos(theta), math.sin(theta)])
+    H = f2 * np.outer(e, e) + (f1 / r) * (np.eye(2) - np.outer(e, e))
+    g = f1 * e
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    cval = 0.5 + 0.5 * math.tanh((R - r) / W)
+    pre = np.concatenate([w * 0.33, w * cval, w * 1.0])
+    st = np.array([g[0], g[1], np.trace(H), 0.0, 0.0, 0.0, 0.0, H[0, 0], H[0, 1], H[1, 1]])
+    _, a = oracle_mod.collide_site(p, pre, st)
+    expect = -p["sigma0"] * d["eps"] * d["alpha"] * f1 * f1 / r * e
+    assert a["Fx"] == pytest.approx(expect[0], rel=1e-12, abs=1e-18)
+    assert a["Fy"] == pytest.approx(expect[1], rel=1e-12, abs=1e-18)
+    # the potential form at the same site differs off equilibrium
+    _, a0 = oracle_mod.collide_site(dict(p, csf_form=0), pre, st)
+    assert abs(a0["Fx"] - a["Fx"]) > 1e-6 * abs(a["Fx"])
+
+
+def test_curvature_force_vanishes_on_flat_profile(oracle_mod):
+    """A planar profile c(y) has no curvature: with grad c along y and the
+    Hessian's only entry d2c/dy2, the capillary force of the curvature form is
+    zero whatever the profile, leaving the Marangoni part alone."""
+    from paper_1412_6238_amd import workloads as wl
+    p = wl.base_params(8, 8, sigma0=0.05, sigmaT=2e-3, Tref=1.0, csf_form=1)
+    d = oracle_mod.derived(p)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    pre = np.concatenate([w * 0.33, w * 0.4, w * 1.3])
+    gy, hyy, gTx, gTy = 0.11, -0.02, 0.03, -0.01
+    st = np.array([0.0, gy, hyy, gTx, gTy, 0.0, 0.0, 0.0, 0.0, hyy])
+    _, a = oracle_mod.collide_site(p, pre, st)
+    # Marangoni part: eps alpha (|g|^2 grad sigma - (g . grad sigma) g) with
+    # grad sigma = -sigmaT grad T; along x only for g along y
+    ea = d["eps"] * d["alpha"]
+    assert a["Fx"] == pytest.approx(ea * gy * gy * (-p["sigmaT"] * gTx), rel=1e-13)
+    assert a["Fy"] == 0.0

@@ -94,7 +94,15 @@ typedef struct {
   int32_t diag_every;    /* > 0: diagnostics of every diag_every-th state
                             during lbe_csf_step (kept on the device, fetched
                             by lbe_csf_diag_history); 0: none               */
-  int32_t reserved;      /* must be 0                                         */
+  int32_t csf_form;      /* capillary part of the CSF force (Eq. 3):
+                            0: potential form kcap sigma mu grad c (exact on
+                               the equilibrium profile; the adjoint covers
+                               this form only);
+                            1: curvature form -sigma (div n) n delta as
+                               printed, with n = grad c/|grad c| and
+                               delta = eps alpha |grad c|^2, evaluated as
+                               -sigma eps alpha (t.H.t) grad c (t the unit
+                               tangent, H the nine-point Hessian of c)      */
 } lbe_csf_params;
 
 /* Global diagnostics of a state F_n (FP64 sums; u_r of Sec. IV C). */

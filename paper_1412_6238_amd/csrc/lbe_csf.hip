@@ -129,7 +129,7 @@ bool params_valid(const lbe_csf_params *p, std::string *why) {
       !fin(p->force[1]) || !fin(p->p0) || !fin(p->T_shift) || !fin(p->T_grad))
     return bad("non-finite parameter");
   if (p->diag_every < 0) return bad("diag_every must be >= 0");
-  if (p->reserved != 0) return bad("reserved must be 0");
+  if (p->csf_form != 0 && p->csf_form != 1) return bad("csf_form must be 0 or 1");
   return true;
 }
 
@@ -264,6 +264,10 @@ void launch_prec(int mode, const Launch &la, const StepArgs &a, hipStream_t st) 
     case kDiag: launch_mode<S, R, DEV, kDiag>(la, a, st); break;
     case kStore | kTape: launch_mode<S, R, DEV, kStore | kTape>(la, a, st); break;
     case kTape: launch_mode<S, R, DEV, kTape>(la, a, st); break;
+    case kStore | kCurv: launch_mode<S, R, DEV, kStore | kCurv>(la, a, st); break;
+    case kStore | kDiag | kCurv: launch_mode<S, R, DEV, kStore | kDiag | kCurv>(la, a, st); break;
+    case kFields | kCurv: launch_mode<S, R, DEV, kFields | kCurv>(la, a, st); break;
+    case kDiag | kCurv: launch_mode<S, R, DEV, kDiag | kCurv>(la, a, st); break;
     default: launch_mode<S, R, DEV, kFields | kDiag>(la, a, st); break;
   }
 }
@@ -279,6 +283,7 @@ int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
   a.uy = uy;
   a.p = p;
   a.T = T;
+  if (h->P.csf_form == 1) mode |= kCurv;
   if (h->P.precision == LBE_CSF_FP64)
     launch_prec<double, double, false>(mode, h->la, a, h->stream);
   else
@@ -507,6 +512,8 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
 int lbe_csf_step(lbe_csf *h, int64_t nsteps, int32_t record) {
   if (!h) return LBE_CSF_EINVAL;
   if (nsteps < 0) return fail(h, LBE_CSF_EINVAL, "nsteps < 0");
+  if (record && h->P.csf_form != 0)
+    return fail(h, LBE_CSF_EINVAL, "the adjoint covers the potential form (csf_form 0) only");
   if (record && (nsteps == 0 || nsteps > h->record_cap))
     return fail(h, LBE_CSF_EINVAL,
                 "record needs 0 < nsteps <= record_steps of the workspace (" +

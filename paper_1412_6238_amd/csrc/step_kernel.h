@@ -6,7 +6,8 @@
 //   stencils     grad c, lap c, grad T, grad p (isotropic nine-point; wall
 //                ghosts: c and p mirrored, T_ghost = 2 T_wall - T)
 //   closures     mu = mu0(c) - eps^2 lap c (Eq. 16), sigma(T) (Eq. 5),
-//                CSF force F (Eqs. 3-4 in potential form), u (Eq. 9 with the
+//                CSF force F (Eq. 3, capillary part in the potential form,
+//                or with kCurv in the curvature form), u (Eq. 9 with the
 //                half force (1/2) cs^2 F), relaxation rates, Fbar = F - grad p
 //   collisions   f (Eqs. 6-8), g (Eqs. 12-14), hbar (Eqs. 22, 25)
 //   streaming    push to x + xi (x periodic); halfway bounce-back for f, g
@@ -107,15 +108,27 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
   const size_t n = (size_t)nx * (size_t)ny;
   // order parameter and its stencils in FP64
   const double cd = cC[1];
-  double gcx_d, gcy_d, lap_d, mu_d;
+  double gcx_d, gcy_d, lap_d, mu_d, tHt = 0.0;
   {
     const double e = cC[2], w = cC[0], nn = cN[1], s = cS[1];
     const double ne = cN[2], nw = cN[0], sw = cS[0], se = cS[2];
     gcx_d = (e - w) * (1.0 / 3.0) + (ne + se - nw - sw) * (1.0 / 12.0);
     gcy_d = (nn - s) * (1.0 / 3.0) + (ne + nw - se - sw) * (1.0 / 12.0);
-    lap_d = (2.0 / 3.0) * ((e - cd) + (w - cd) + (nn - cd) + (s - cd)) +
-            (1.0 / 6.0) * ((ne - cd) + (nw - cd) + (se - cd) + (sw - cd));
+    const double dx2 = (e - cd) + (w - cd), dy2 = (nn - cd) + (s - cd);
+    const double dd = (ne - cd) + (nw - cd) + (se - cd) + (sw - cd);
+    lap_d = (2.0 / 3.0) * (dx2 + dy2) + (1.0 / 6.0) * dd;
     mu_d = a.beta2 * cd * (cd - 1.0) * (2.0 * cd - 1.0) - a.eps2 * lap_d;
+    if (MODE & kCurv) {
+      // Hessian of c on the same nine points (exact on quadratics) and the
+      // second derivative along the unit tangent t = (-gy, gx)/|grad c|,
+      // which equals |grad c| div n for n = grad c/|grad c|
+      const double hxx = (2.0 / 3.0) * dx2 - (1.0 / 3.0) * dy2 + (1.0 / 6.0) * dd;
+      const double hyy = (2.0 / 3.0) * dy2 - (1.0 / 3.0) * dx2 + (1.0 / 6.0) * dd;
+      const double hxy = 0.25 * ((ne - nw) - (se - sw));
+      const double gg = gcx_d * gcx_d + gcy_d * gcy_d;
+      if (gg > 0.0)
+        tHt = (gcy_d * gcy_d * hxx - 2.0 * gcx_d * gcy_d * hxy + gcx_d * gcx_d * hyy) / gg;
+    }
   }
   const R c = R(cd);
   const R Tv = tC[1];   // T, or Delta T = T - Trow in the FP32 form
@@ -160,7 +173,9 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
   const double gsx = -a.sigmaT * gTx, gsy = -a.sigmaT * gTy;
   const double g2 = gcx_d * gcx_d + gcy_d * gcy_d;
   const double gds = gcx_d * gsx + gcy_d * gsy;
-  const double ks = a.kcap * sigma * mu_d;
+  // capillary part along grad c: kcap sigma mu (potential form) or
+  // -sigma eps alpha |grad c| div n (curvature form)
+  const double ks = (MODE & kCurv) ? -a.epsalpha * sigma * tHt : a.kcap * sigma * mu_d;
   const double inv_rho = 1.0 / a.rho;
   const double Fxd = ks * gcx_d + a.epsalpha * (g2 * gsx - gds * gcx_d) + a.rho * a.ax;
   const double Fyd = ks * gcy_d + a.epsalpha * (g2 * gsy - gds * gcy_d) + a.rho * a.ay;

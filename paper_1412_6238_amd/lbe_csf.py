@@ -53,7 +53,7 @@ class lbe_csf_params(ctypes.Structure):
         ("sigma0", ctypes.c_double), ("sigmaT", ctypes.c_double), ("Tref", ctypes.c_double),
         ("force", ctypes.c_double * 2),
         ("p0", ctypes.c_double), ("T_shift", ctypes.c_double), ("T_grad", ctypes.c_double),
-        ("diag_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("diag_every", ctypes.c_int32), ("csf_form", ctypes.c_int32),
     ]
 
 
@@ -122,7 +122,7 @@ def make_params(p: dict, precision="fp64", diag_every=0) -> lbe_csf_params:
     P.force[0], P.force[1] = map(float, p["force"])
     P.p0, P.T_shift = float(p["p0"]), float(p.get("T_shift", 0.0))
     P.T_grad = float(p.get("T_grad", 0.0))
-    P.diag_every, P.reserved = int(diag_every), 0
+    P.diag_every, P.csf_form = int(diag_every), int(p.get("csf_form", 0))
     return P
 
 

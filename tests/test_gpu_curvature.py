@@ -1,0 +1,214 @@
+"""GPU parity of the curvature form of the capillary force (Eq. 3 as printed):
+-sigma (div n) n delta with n = grad c/|grad c|, delta = eps alpha |grad c|^2.
+
+The HIP step with csf_form = 1 against the FP64 CPU oracle (1e-12 relative),
+its row pipelines and strip shapes against each other (bitwise), the FP32
+deviation form against FP64 at the stated step counts (1e-4 relative L2), and
+the 4096 x 4096 workload on sampled windows.  The adjoint covers the potential
+form only; a recorded run with the curvature form is refused.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1412_6238_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi", "ux", "uy", "p", "T")
+
+
+@pytest.fixture(scope="module")
+def lbe():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1412_6238_amd import lbe_csf
+    return lbe_csf
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _cmp(gpu, orc, tol=1e-12, what=""):
+    g, o = dict(gpu), dict(orc)
+    if "ux" in o:
+        g["u"] = np.stack([g.pop("ux"), g.pop("uy")])
+        o["u"] = np.stack([o.pop("ux"), o.pop("uy")])
+    errs = {}
+    for k in o:
+        gk, ok = np.asarray(g[k]), np.asarray(o[k])
+        scale = max(np.abs(ok).max(), 1e-300)
+        assert np.all(np.isfinite(gk)), (what, k)
+        errs[k] = _rel(gk, ok)
+        assert errs[k] <= tol, (what, k, errs[k])
+        assert np.abs(gk - ok).max() <= 10 * tol * scale, (what, k, np.abs(gk - ok).max() / scale)
+    _say(f"  {what}: rel L2 " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+
+
+def _fields_np(sim):
+    return {k: v.cpu().numpy() for k, v in sim.fields().items()}
+
+
+def _curv(case, **kw):
+    case = dict(case)
+    case["params"] = dict(case["params"], csf_form=1, **kw)
+    return case
+
+
+GRIDS = [(8, 8, 1), (37, 21, 1), (70, 9, 0), (130, 7, 1), (600, 5, 0), (64, 64, 1)]
+
+
+@pytest.mark.parametrize("nx,ny,walls", GRIDS)
+def test_curvature_fp64_vs_oracle(lbe, oracle_mod, nx, ny, walls):
+    case = _curv(wl.random_case(nx, ny, seed=3 * nx + ny, walls_y=walls), p0=0.0)
+    p = case["params"]
+    _say(f"case curvature random {nx}x{ny} walls={walls} fp64")
+    sim = lbe.Simulation(p, case["phi0"], case["T0"], case["Twall_bot"], case["Twall_top"])
+    orc = oracle_mod.Oracle(p, case["Twall_bot"], case["Twall_top"]).init(case["phi0"], case["T0"])
+    for n in (1, 3, 12):
+        sim.step(n)
+        orc.step(n)
+        _cmp({"F": sim.get_state().cpu().numpy()}, {"F": orc.state()}, what=f"F after +{n}")
+        _cmp(_fields_np(sim), orc.fields(), what=f"fields after +{n}")
+
+
+def test_curvature_random_state(lbe, oracle_mod):
+    """An arbitrary non-equilibrium state (profiles far from tanh, where the
+    two forms differ most)."""
+    case = _curv(wl.random_case(90, 33, seed=5, walls_y=1))
+    F = wl.random_state(90, 33, seed=17)
+    p = case["params"]
+    _say("case curvature random state 90x33 fp64")
+    sim = lbe.Simulation(p, case["phi0"], case["T0"], case["Twall_bot"], case["Twall_top"])
+    orc = oracle_mod.Oracle(p, case["Twall_bot"], case["Twall_top"]).init(case["phi0"], case["T0"])
+    sim.set_state(F)
+    orc.set_state(F)
+    sim.step(4)
+    orc.step(4)
+    _cmp({"F": sim.get_state().cpu().numpy()}, {"F": orc.state()}, what="F")
+
+
+@pytest.mark.parametrize("name,nsteps", [("e2", 2000), ("e3", 300)])
+def test_curvature_paper_cases_vs_oracle(lbe, oracle_mod, name, nsteps):
+    """The paper's planar (200 x 100) and droplet (160 x 300) cases with the
+    curvature form, p0 = 0 gauge."""
+    w = wl.paper_case(name, csf_form=1, p0=0.0)
+    p = w["params"]
+    _say(f"case curvature paper {name} fp64 {nsteps} steps")
+    sim = lbe.Simulation(p, w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"])
+    orc = oracle_mod.Oracle(p, w["Twall_bot"], w["Twall_top"]).init(w["phi0"], w["T0"])
+    sim.step(nsteps)
+    orc.step(nsteps)
+    _cmp(_fields_np(sim), orc.fields(), what=name)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
+def test_curvature_launch_shapes_agree(lbe, monkeypatch, precision):
+    """Row pipelines 0/1/2 and strip widths of 1, 2, 4, 8 waves give the same
+    state, bit for bit."""
+    case = _curv(wl.random_case(300, 40, seed=31, walls_y=1))
+    out = []
+    for pipe, nw, rows in (("1", "4", "40"), ("0", "1", "7"), ("2", "2", "9"), ("2", "8", "13")):
+        monkeypatch.setenv("LBE_CSF_PIPE", pipe)
+        monkeypatch.setenv("LBE_CSF_NW", nw)
+        monkeypatch.setenv("LBE_CSF_ROWS", rows)
+        _say(f"case curvature launch pipe={pipe} nw={nw} rows={rows} {precision}")
+        sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                             case["Twall_top"], precision=precision)
+        sim.step(5)
+        out.append(sim.get_state().cpu().numpy())
+    for o in out[1:]:
+        np.testing.assert_array_equal(o, out[0])
+
+
+@pytest.mark.parametrize("name,nsteps", [("paper_e2", 37500), ("paper_e3", 40000),
+                                         ("multi_droplet", 2000)])
+def test_curvature_fp32_dev_vs_fp64(lbe, name, nsteps):
+    """FP32 deviation storage against the FP64 path with the curvature form:
+    relative L2 on phi, u and T within 1e-4 after the stated steps."""
+    import torch
+    if name.startswith("paper_"):
+        w = wl.paper_case(name[6:], csf_form=1)
+    else:
+        w = wl.make(name, csf_form=1)
+    _say(f"case curvature fp32_dev vs fp64 {name} {nsteps}")
+    res = {}
+    for prec in ("fp64", "fp32_dev"):
+        sim = lbe.Simulation(w["params"], w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"],
+                             precision=prec)
+        sim.step(nsteps)
+        res[prec] = sim.fields()
+        del sim
+    a, b = res["fp32_dev"], res["fp64"]
+    rel = lambda x, y: (torch.linalg.norm(x - y) / torch.linalg.norm(y)).item()
+    errs = {"phi": rel(a["phi"], b["phi"]),
+            "u": rel(torch.stack([a["ux"], a["uy"]]), torch.stack([b["ux"], b["uy"]])),
+            "T": rel(a["T"], b["T"])}
+    _say("  errors " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= 1e-4, (k, v)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32_dev", 1e-5), ("fp64", 1e-12)])
+def test_curvature_full_size_sampled(lbe, oracle_mod, precision, tol):
+    """4096 x 4096 multi-droplet workload with the curvature form, in the
+    benchmark's launch configuration: k GPU steps, the oracle on windows
+    centred on droplet interfaces, fields compared on the valid centres."""
+    w = wl.make("multi_droplet", csf_form=1)
+    p = w["params"]
+    nx, ny = p["nx"], p["ny"]
+    k = 3
+    _say(f"case curvature full-size multi_droplet {precision} {k} steps")
+    sim = lbe.Simulation(p, w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"], precision=precision)
+    sim.step(k)
+    g = {kk: v.cpu().numpy() for kk, v in sim.fields().items()}
+    del sim
+    umax = np.hypot(g["ux"], g["uy"]).max()
+    trange = w["T0"].max() - w["T0"].min()
+    rng = np.random.default_rng(7)
+    m = 2 + 2 * k
+    size = 2 * m + 8
+    iy, ix = np.nonzero(np.abs(w["phi0"]) < 0.5)
+    wins = []
+    for t in rng.choice(len(iy), 10, replace=False):
+        y0 = int(min(max(iy[t] - m - 4, 0), ny - size))
+        wins.append((int((ix[t] - m - 4) % nx), y0, size, size))
+    checked = 0
+    for (x0, y0, wx, wy) in wins:
+        cols = np.arange(x0, x0 + wx) % nx
+        sub = lambda a: np.ascontiguousarray(a[y0:y0 + wy][:, cols])
+        o = oracle_mod.Oracle(p, w["Twall_bot"], w["Twall_top"], window=(x0, y0, wx, wy))
+        o.init(sub(w["phi0"]), sub(w["T0"]))
+        o.step(k)
+        of = o.fields()
+        jj, ii = np.meshgrid(np.arange(wy), np.arange(wx), indexing="ij")
+        dist_x = np.minimum(ii, wx - 1 - ii)
+        dist_bot = jj if y0 > 0 else np.full_like(jj, 10 ** 6)
+        dist_top = (wy - 1 - jj) if y0 + wy < ny else np.full_like(jj, 10 ** 6)
+        valid = np.minimum(np.minimum(dist_x, dist_bot), dist_top) >= 2 + 2 * k
+        gw = {f: sub(g[f])[valid] for f in FIELDS}
+        ow = {f: of[f][valid] for f in FIELDS}
+        du = np.hypot(gw["ux"] - ow["ux"], gw["uy"] - ow["uy"]).max()
+        assert du <= tol * umax, ("u", x0, y0, du / umax)
+        assert np.abs(gw["phi"] - ow["phi"]).max() <= tol, ("phi", x0, y0)
+        assert np.abs(gw["T"] - ow["T"]).max() <= tol * trange, ("T", x0, y0)
+        assert np.abs(gw["p"] - ow["p"]).max() <= tol * np.abs(ow["p"]).max(), ("p", x0, y0)
+        checked += int(valid.sum())
+    _say(f"  compared {checked} sites in {len(wins)} windows")
+
+
+def test_curvature_form_refuses_recording(lbe):
+    case = _curv(wl.random_case(16, 16, seed=2))
+    sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                         case["Twall_top"], record_steps=8)
+    with pytest.raises(lbe.LbeCsfError) as e:
+        sim.step(4, record=True)
+    assert e.value.status == lbe.LBE_CSF_EINVAL

@@ -40,10 +40,11 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload, precision, sites):
+def traffic_from_profile(workload, precision, sites, csf_form=0):
     """Measured HBM bytes per launch from the committed counter summary, if it
     was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_step_{workload}_{precision}.json")
+    form = "_curvature" if csf_form == 1 else ""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_{workload}_{precision}{form}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -131,6 +132,9 @@ def main():
     ap.add_argument("--precision", default="fp32_dev", choices=("fp32_dev", "fp64"))
     ap.add_argument("--workload", default="multi_droplet")
     ap.add_argument("--diag-every", type=int, default=100)
+    ap.add_argument("--csf-form", type=int, default=0, choices=(0, 1),
+                    help="capillary part of the CSF force: 0 potential form (default), "
+                         "1 curvature form as printed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--adjoint", action="store_true",
@@ -162,7 +166,7 @@ def main():
     if args.adjoint:
         adjoint_bench(args, torch, lbe_csf, wl)
         return
-    w = wl.make(args.workload)
+    w = wl.make(args.workload, csf_form=args.csf_form)
     p = w["params"]
     nx, ny = p["nx"], p["ny"]
     sites = nx * ny
@@ -194,7 +198,7 @@ def main():
     # region (the region also holds steps/diag_every tiny reduction launches)
     bps = BYTES_PER_SITE[args.precision]
     achieved = bps * sites / (ms_per_step / 1e3) / 1e9
-    traffic = traffic_from_profile(args.workload, args.precision, sites)
+    traffic = traffic_from_profile(args.workload, args.precision, sites, args.csf_form)
     out = {
         "metric": "MLUPS (3 coupled D2Q9 lattices)",
         "value": round(mlups, 2),
@@ -210,6 +214,7 @@ def main():
         "data": "synthetic (seeded droplets, linear temperature)",
         "config": {"workload": f"{args.workload} {nx}x{ny}", "precision": args.precision,
                    "sites": sites, "diag_every": args.diag_every,
+                   "capillary_form": "curvature" if args.csf_form == 1 else "potential",
                    "bytes_per_site_update": bps},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),

@@ -94,7 +94,7 @@ typedef struct {
   int32_t diag_every;    /* > 0: diagnostics of every diag_every-th state
                             during lbe_csf_step (kept on the device, fetched
                             by lbe_csf_diag_history); 0: none               */
-  int32_t csf_form;      /* capillary part of the CSF force (Eq. 3):
+  int32_t csf_form;      /* capillary part of the CSF force (Eq. 4):
                             0: potential form kcap sigma mu grad c (exact on
                                the equilibrium profile; the adjoint covers
                                this form only);

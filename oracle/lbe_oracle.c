@@ -14,9 +14,9 @@
  *   B  stencils         grad c, lap c, grad T, grad p (the paper needs them
  *                       in Eqs. 4, 12, 16, 25 but does not give a scheme;
  *                       isotropic nine-point stencils are the reading used)
- *                       and the Hessian of c (curvature form of Eq. 3 only)
+ *                       and the Hessian of c (curvature form of Eq. 4 only)
  *   C  closures         mu = mu0(c) - eps^2 lap c (Sec. II, Eq. 16),
- *                       sigma(T) (Eq. 5), CSF force (Eq. 3, with its
+ *                       sigma(T) (Eq. 5), CSF force (Eqs. 3-4, with its
  *                       capillary part in the potential or curvature form),
  *                       u (Eq. 9), relaxation rates (Eqs. 6, 12, 25)
  *   D  collide          f (Eqs. 6-8), g (Eqs. 12-14), hbar (Eqs. 22, 25)
@@ -242,7 +242,7 @@ static void closure_site(const orc *o, double c, double T, double jx, double jy,
   /* linear surface tension, Eq. 5; READING: sigmaT here is -sigma_T */
   r->sigma = P->sigma0 - P->sigmaT * (T - P->Tref);
   const double gsx = -P->sigmaT * gTx, gsy = -P->sigmaT * gTy;
-  /* CSF force, Eq. 3.  The tangential (Marangoni) part is grad_s(sigma)
+  /* CSF force, Eqs. 3-4.  The tangential (Marangoni) part is grad_s(sigma)
    * delta with delta = eps alpha |grad c|^2.  The normal (capillary) part,
    * -sigma kappa n delta with n = grad c / |grad c| and kappa = div n, is
    * taken in one of two forms:

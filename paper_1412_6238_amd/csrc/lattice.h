@@ -27,7 +27,7 @@ enum : int {
   kFields = 2,  // write phi, u, p, T
   kDiag = 4,    // per-block FP64 partial sums of the diagnostics
   kTape = 8,    // write the moments of the source state to the tape
-  kCurv = 16    // capillary force in the curvature form of Eq. 3
+  kCurv = 16    // capillary force in the curvature form of Eq. 4
 };
 
 constexpr int kNumPartials = 7;  // mass, energy, cy, cx, mass_thr, cuy_thr, nonfinite

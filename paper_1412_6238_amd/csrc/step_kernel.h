@@ -6,7 +6,7 @@
 //   stencils     grad c, lap c, grad T, grad p (isotropic nine-point; wall
 //                ghosts: c and p mirrored, T_ghost = 2 T_wall - T)
 //   closures     mu = mu0(c) - eps^2 lap c (Eq. 16), sigma(T) (Eq. 5),
-//                CSF force F (Eq. 3, capillary part in the potential form,
+//                CSF force F (Eqs. 3-4, capillary part in the potential form,
 //                or with kCurv in the curvature form), u (Eq. 9 with the
 //                half force (1/2) cs^2 F), relaxation rates, Fbar = F - grad p
 //   collisions   f (Eqs. 6-8), g (Eqs. 12-14), hbar (Eqs. 22, 25)

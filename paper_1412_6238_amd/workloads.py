@@ -15,6 +15,7 @@ case and a differentiated droplet case:
   droplet           512 x 1024  one migrating droplet (Sec. IV C)
   adjoint_droplet   256 x 512   droplet case differentiated w.r.t. sigmaT, T_wall
   multi_droplet     4096 x 4096 200 seeded droplets, throughput
+  multi_droplet_slab  4096 x 516  one of eight y-slabs of it, with 2 + 2 halo rows
 
 Grid convention: sites (i, j) at x = i + 1/2, y = j + 1/2; x periodic; when
 ``walls_y`` is 1 the walls sit halfway, at y = 0 and y = ny.  Arrays are
@@ -224,6 +225,18 @@ def make(name: str, **overrides) -> dict:
         Y, _ = coords(nx, ny)
         T0 = 0.002 * Y
         tb, tt = np.zeros(nx), np.full(nx, 0.002 * ny)
+        nsteps, prec = 2000, "fp32_dev"
+    elif name == "multi_droplet_slab":
+        # one GPU's share of the 4096 x 4096 run split into eight y-slabs:
+        # 512 rows plus two halo rows on each side, taken from the middle of
+        # the full field; walls at the band's edges hold the full field's
+        # temperatures there (the stand-in for the exchanged halo rows)
+        full = make("multi_droplet")
+        y0, y1 = 2048 - 258, 2048 + 258
+        p = dict(full["params"], ny=y1 - y0, T_shift=0.002 * y0)
+        phi0 = full["phi0"][y0:y1]
+        T0 = full["T0"][y0:y1]
+        tb, tt = np.full(4096, 0.002 * y0), np.full(4096, 0.002 * y1)
         nsteps, prec = 2000, "fp32_dev"
     else:
         raise KeyError(name)

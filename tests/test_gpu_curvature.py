@@ -1,4 +1,4 @@
-"""GPU parity of the curvature form of the capillary force (Eq. 3 as printed):
+"""GPU parity of the curvature form of the capillary force (Eq. 4 as printed):
 -sigma (div n) n delta with n = grad c/|grad c|, delta = eps alpha |grad c|^2.
 
 The HIP step with csf_form = 1 against the FP64 CPU oracle (1e-12 relative),

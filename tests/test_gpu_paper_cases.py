@@ -134,7 +134,7 @@ def test_e1_layered_poiseuille(lbe, oracle_mod, lam_r, h_r):
                                                     (1.0, 0, 0.30, 1e-3)])
 def test_e2_planar_marangoni(lbe, oracle_mod, lam_r, form, bar_u, bar_T):
     """Sec. IV B after three thermal times of the less conducting layer.  With
-    the curvature form of Eq. 3 the velocity is within 6% (lambda_r = 1) and
+    the curvature form of Eq. 4 the velocity is within 6% (lambda_r = 1) and
     10% (lambda_r = 0.1) of the sharp-interface solution, the deviation
     growing as lambda_r falls, as the paper reports.  The potential form at
     the printed mobility is 25% low: its capillary term resists the

@@ -144,7 +144,7 @@ def test_paper_printed_constants(oracle_mod):
 
 @pytest.mark.parametrize("theta", [0.3, 1.1, 2.5, 4.0, 5.6])
 def test_curvature_force_closed_form(oracle_mod, theta):
-    """Curvature form of the capillary force, Eq. 3: -sigma kappa n delta with
+    """Curvature form of the capillary force, Eq. 4: -sigma kappa n delta with
     n = grad c/|grad c|, kappa = div n, delta = eps alpha |grad c|^2.  For a
     radial profile c = f(r) the gradient is f' r_hat and the Hessian is
     f'' r_hat r_hat + (f'/r)(I - r_hat r_hat), so div n = -1/r (n points

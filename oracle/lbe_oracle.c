@@ -11,6 +11,8 @@
  * method defines them:
  *   A  moments          c = sum g  (Eq. 15), rho cv T = sum hbar (Eq. 26),
  *                       p = sum f, rho cs^2 u from sum xi f (Eq. 9)
+ *                       (with two densities, rho = rho(c) and p gains
+ *                       (dt/2) u.grad(rho cs^2) once u is known, Eq. 9)
  *   B  stencils         grad c, lap c, grad T, grad p (the paper needs them
  *                       in Eqs. 4, 12, 16, 25 but does not give a scheme;
  *                       isotropic nine-point stencils are the reading used)
@@ -68,6 +70,7 @@ typedef struct {
   double sigma0, sigmaT, Tref; /* sigma = sigma0 - sigmaT (T - Tref) */
   double force[2];             /* body acceleration a */
   double p0;                   /* reference pressure of the initial state */
+  double rho2;                 /* density of the c = 1 fluid (rho: c = 0) */
 } orc_params;
 
 /* Diagnostic record, one FP64 value each. */
@@ -138,10 +141,17 @@ static int neighbour(const orc *o, int i, int j, int dx, int dy, int *loc,
   return kind;
 }
 
+/* READING: the density of the mixture is linear in the order parameter,
+ * rho(c) = rho1 + c (rho2 - rho1), unclamped so that grad rho = (rho2 - rho1)
+ * grad c exactly.  The paper carries the density terms of Eqs. 6, 9 and the
+ * F-bar of Sec. III but never states the closure rho(c). */
+static double rho_of(const orc_params *P, double c) {
+  return P->rho + c * (P->rho2 - P->rho);
+}
+
 /* ---- pass A: moments of the pre-collision state --------------------------- */
 static void pass_moments(orc *o) {
   const int n = o->n;
-  const double rcv = o->P.rho * o->P.cv;
 #pragma omp parallel for schedule(static)
   for (int s = 0; s < n; ++s) {
     double sf = 0.0, sg = 0.0, sh = 0.0, sx = 0.0, sy = 0.0;
@@ -153,11 +163,11 @@ static void pass_moments(orc *o) {
       sg += o->F[(NQ + k) * n + s];
       sh += o->F[(2 * NQ + k) * n + s];
     }
-    o->p[s] = sf;        /* Eq. 9: the u.grad(rho cs^2) term is zero (uniform rho) */
+    o->p[s] = sf;        /* Eq. 9 without its u.grad(rho cs^2) term (pass C2) */
     o->jx[s] = sx;
     o->jy[s] = sy;
     o->c[s] = sg;        /* Eq. 15 */
-    o->T[s] = sh / rcv;  /* Eq. 26 */
+    o->T[s] = sh / (rho_of(&o->P, sg) * o->P.cv);  /* Eq. 26 */
   }
 }
 
@@ -224,7 +234,10 @@ static void pass_stencils(orc *o) {
 
 /* ---- pass C: chemical potential, CSF force, velocity ----------------------- */
 typedef struct {
-  double mu, sigma, Fx, Fy, ux, uy, wf, wT, wg, Fbx, Fby;
+  double mu, sigma, Fx, Fy, ux, uy, wf, wT, wg;
+  double rho, grx, gry;  /* rho(c) and grad rho */
+  double Fgx, Fgy;       /* F - grad p, the force term of the g equation (Eq. 12) */
+  double Fbx, Fby;       /* F-bar = grad(rho cs^2) - grad p + F (Sec. III) */
 } closure_t;
 
 /* mu0 = dE0/dc for E0 = beta c^2 (c-1)^2 (Sec. II, c1 = 0, c2 = 1). */
@@ -237,6 +250,10 @@ static void closure_site(const orc *o, double c, double T, double jx, double jy,
                          double gTy, double gpx, double gpy, double hxx,
                          double hxy, double hyy, closure_t *r) {
   const orc_params *P = &o->P;
+  const double rho = rho_of(P, c);
+  r->rho = rho;
+  r->grx = (P->rho2 - P->rho) * gcx;
+  r->gry = (P->rho2 - P->rho) * gcy;
   /* chemical potential, Sec. II below Eq. 16 */
   r->mu = mu_bulk(P->beta, c) - o->eps * o->eps * lapc;
   /* linear surface tension, Eq. 5; READING: sigmaT here is -sigma_T */
@@ -265,12 +282,12 @@ static void closure_site(const orc *o, double c, double T, double jx, double jy,
     capx = o->kcap * r->sigma * r->mu * gcx;
     capy = o->kcap * r->sigma * r->mu * gcy;
   }
-  r->Fx = capx + ea * (g2 * gsx - gdots * gcx) + P->rho * P->force[0];
-  r->Fy = capy + ea * (g2 * gsy - gdots * gcy) + P->rho * P->force[1];
+  r->Fx = capx + ea * (g2 * gsx - gdots * gcx) + rho * P->force[0];
+  r->Fy = capy + ea * (g2 * gsy - gdots * gcy) + rho * P->force[1];
   /* Eq. 9.  READING: the half-force enters as (dt/2) cs^2 F, the first moment
    * of the forcing term of Eq. 6, so u = (sum xi f)/(rho cs^2) + F/(2 rho). */
-  r->ux = jx / (P->rho * OCS2) + r->Fx / (2.0 * P->rho);
-  r->uy = jy / (P->rho * OCS2) + r->Fy / (2.0 * P->rho);
+  r->ux = jx / (rho * OCS2) + r->Fx / (2.0 * rho);
+  r->uy = jy / (rho * OCS2) + r->Fy / (2.0 * rho);
   /* READING: relaxation times vary linearly with the clamped order parameter.
    * (Comparisons written so that a NaN passes through unchanged.) */
   double ch = c < 0.0 ? 0.0 : (c > 1.0 ? 1.0 : c);
@@ -279,9 +296,12 @@ static void closure_site(const orc *o, double c, double T, double jx, double jy,
   r->wf = 1.0 / tf;
   r->wT = 1.0 / tT;       /* 2 dt / (2 tau_h + dt) with tau_T = tau_h + 1/2 */
   r->wg = 1.0 / P->tau_g;
-  /* F-bar = grad(rho cs^2) - grad p + F, with uniform rho (Sec. III) */
-  r->Fbx = r->Fx - gpx;
-  r->Fby = r->Fy - gpy;
+  /* F - grad p drives c (Eq. 12); F-bar = grad(rho cs^2) - grad p + F drives
+   * hbar (Sec. III); they differ by the density gradient */
+  r->Fgx = r->Fx - gpx;
+  r->Fgy = r->Fy - gpy;
+  r->Fbx = r->Fgx + OCS2 * r->grx;
+  r->Fby = r->Fgy + OCS2 * r->gry;
 }
 
 static void pass_closures(orc *o) {
@@ -299,6 +319,20 @@ static void pass_closures(orc *o) {
   }
 }
 
+/* ---- pass C2: the pressure of Eq. 9 with two densities ----------------------
+ * p = sum f + (dt/2) u.grad(rho cs^2), then the stencils again so that grad p
+ * is taken of this p.  With one density the term is zero and the pass is
+ * skipped. */
+static void pass_pressure(orc *o) {
+  const orc_params *P = &o->P;
+  if (P->rho2 == P->rho) return;
+  const double dr = P->rho2 - P->rho;
+#pragma omp parallel for schedule(static)
+  for (int s = 0; s < o->n; ++s)
+    o->p[s] += 0.5 * OCS2 * dr * (o->ux[s] * o->gcx[s] + o->uy[s] * o->gcy[s]);
+  pass_stencils(o);
+}
+
 /* ---- pass D: the three collisions at one site --------------------------------
  * in/out hold 27 values (f, g, hbar).  gamma_i(u) is Eq. 8. */
 static void collide_site(const orc *o, const double *in, double c, double T,
@@ -306,7 +340,7 @@ static void collide_site(const orc *o, const double *in, double c, double T,
   const orc_params *P = &o->P;
   const double ux = r->ux, uy = r->uy;
   const double usq = ux * ux + uy * uy;
-  const double rho = P->rho;
+  const double rho = r->rho;
   for (int k = 0; k < NQ; ++k) {
     const double e = OX[k] * ux + OY[k] * uy;
     const double gam =
@@ -316,7 +350,10 @@ static void collide_site(const orc *o, const double *in, double c, double T,
     const double feq =
         OW[k] * (p + rho * OCS2 *
                          (e / OCS2 + 0.5 * ((e / OCS2) * (e / OCS2) - usq / OCS2)));
-    const double Sf = (r->Fx * cxu + r->Fy * cyu) * gam;
+    /* F.(xi - u) Gamma_i(u) + (xi - u).grad(rho cs^2) (Gamma_i(u) - Gamma_i(0)),
+     * with Gamma_i(0) = w_i */
+    const double Sf = (r->Fx * cxu + r->Fy * cyu) * gam +
+                      OCS2 * (r->grx * cxu + r->gry * cyu) * (gam - OW[k]);
     out[k] = in[k] - r->wf * (in[k] - feq) + (1.0 - 0.5 * r->wf) * Sf;
     /* order parameter, Eqs. 12-14 (w0 is the rest weight) */
     const double H = (k == 0)
@@ -324,7 +361,7 @@ static void collide_site(const orc *o, const double *in, double c, double T,
                          : o->Gam * r->mu / OCS2;
     const double geq =
         OW[k] * (H + c * (e / OCS2 + 0.5 * ((e / OCS2) * (e / OCS2) - usq / OCS2)));
-    const double Sg = c * (cxu * r->Fbx + cyu * r->Fby) / (rho * OCS2) * gam;
+    const double Sg = c * (cxu * r->Fgx + cyu * r->Fgy) / (rho * OCS2) * gam;
     out[NQ + k] = in[NQ + k] - r->wg * (in[NQ + k] - geq) + (1.0 - 0.5 * r->wg) * Sg;
     /* temperature, Eqs. 22 and 25 */
     const double heq = rho * P->cv * T * gam;
@@ -358,11 +395,12 @@ static void pass_collide(orc *o) {
 static void pass_stream(orc *o) {
   const orc_params *P = &o->P;
   const int n = o->n;
-  const double rcv = P->rho * P->cv;
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < P->wy; ++j)
     for (int i = 0; i < P->wx; ++i) {
       const int s = j * P->wx + i;
+      /* rho cv of the boundary node (its pre-collision c) */
+      const double rcv = rho_of(P, o->c[s]) * P->cv;
       for (int k = 0; k < NQ; ++k) {
         /* the source x - xi_k is the neighbour in direction opp(k) */
         const int kind = k == 0 ? NB_IN : o->nb_kind[OOPP[k] * n + s];
@@ -483,7 +521,7 @@ OAPI void orc_init(orc *o, const double *phi0, const double *T0) {
         const double H = (k == 0) ? (c - (1.0 - OW[0]) * o->Gam * mu / OCS2) / OW[0]
                                   : o->Gam * mu / OCS2;
         o->F[(NQ + k) * n + s] = OW[k] * H;
-        o->F[(2 * NQ + k) * n + s] = OW[k] * P->rho * P->cv * T0[s];
+        o->F[(2 * NQ + k) * n + s] = OW[k] * rho_of(P, c) * P->cv * T0[s];
       }
     }
 }
@@ -507,7 +545,7 @@ static void diag_from_passes(const orc *o, double *d) {
       const double y = (double)(P->y0 + j) + 0.5;
       const double x = (double)(P->x0 + i) + 0.5;
       d[ORC_D_MASS] += c;
-      d[ORC_D_ENERGY] += P->rho * P->cv * o->T[s];
+      d[ORC_D_ENERGY] += rho_of(P, c) * P->cv * o->T[s];
       d[ORC_D_SUM_CY] += c * y;
       d[ORC_D_SUM_CX] += c * x;
       /* u_r of Sec. IV C: sums over the sites with c >= 1/2 */
@@ -526,6 +564,7 @@ OAPI void orc_step(orc *o, int nsteps) {
     pass_moments(o);
     pass_stencils(o);
     pass_closures(o);
+    pass_pressure(o);
     pass_collide(o);
     pass_stream(o);
   }
@@ -538,6 +577,7 @@ OAPI void orc_fields(orc *o, double *phi, double *ux, double *uy, double *p,
   pass_moments(o);
   pass_stencils(o);
   pass_closures(o);
+  pass_pressure(o);
   for (int s = 0; s < o->n; ++s) {
     if (phi) phi[s] = 2.0 * o->c[s] - 1.0;
     if (ux) ux[s] = o->ux[s];
@@ -553,6 +593,7 @@ OAPI void orc_intermediates(orc *o, double *out) {
   pass_moments(o);
   pass_stencils(o);
   pass_closures(o);
+  pass_pressure(o);
   const double *src[] = {o->c,   o->T,   o->p,    o->jx,  o->jy,  o->gcx,
                          o->gcy, o->lapc, o->gTx, o->gTy, o->gpx, o->gpy,
                          o->mu,  o->Fx,  o->Fy,   o->ux,  o->uy,
@@ -565,13 +606,15 @@ OAPI void orc_diag(orc *o, double *d) {
   pass_moments(o);
   pass_stencils(o);
   pass_closures(o);
+  pass_pressure(o);
   diag_from_passes(o, d);
 }
 
 /* Single-site collision for pinning: in[27] pre-collision values at the site,
  * st[10] = (gcx, gcy, lapc, gTx, gTy, gpx, gpy, hxx, hxy, hyy) stencil values
  * (the Hessian of c is read by the curvature form only); writes out[27]
- * and aux[11] = (c, T, p, mu, Fx, Fy, ux, uy, wf, wT, wg). */
+ * and aux[11] = (c, T, p, mu, Fx, Fy, ux, uy, wf, wT, wg), p being the
+ * pressure of Eq. 9. */
 OAPI void orc_collide_site(const orc_params *P, const double *in,
                            const double *st, double *out, double *aux) {
   orc o;
@@ -586,10 +629,11 @@ OAPI void orc_collide_site(const orc_params *P, const double *in,
     c += in[NQ + k];
     T += in[2 * NQ + k];
   }
-  T /= P->rho * P->cv;
+  T /= rho_of(P, c) * P->cv;
   closure_t r;
   closure_site(&o, c, T, jx, jy, st[0], st[1], st[2], st[3], st[4], st[5], st[6],
                st[7], st[8], st[9], &r);
+  p += 0.5 * OCS2 * (r.ux * r.grx + r.uy * r.gry);   /* Eq. 9 */
   collide_site(&o, in, c, T, p, &r, out);
   if (aux) {
     aux[0] = c; aux[1] = T; aux[2] = p; aux[3] = r.mu; aux[4] = r.Fx;

@@ -40,7 +40,7 @@ class _Params(ctypes.Structure):
         ("width", ctypes.c_double), ("beta", ctypes.c_double),
         ("sigma0", ctypes.c_double), ("sigmaT", ctypes.c_double),
         ("Tref", ctypes.c_double), ("force", ctypes.c_double * 2),
-        ("p0", ctypes.c_double),
+        ("p0", ctypes.c_double), ("rho2", ctypes.c_double),
     ]
 
 
@@ -108,6 +108,7 @@ def _make_params(p: dict, window=None) -> _Params:
                                   float(p["Tref"]))
     P.force[0], P.force[1] = map(float, p["force"])
     P.p0 = float(p["p0"])
+    P.rho2 = float(p.get("rho2", p["rho"]))
     return P
 
 

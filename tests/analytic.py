@@ -80,27 +80,39 @@ def ygb_velocity(sigma_T, gradT, R, eta2, lam_r, eta_r):
     return 2 * U / ((2 + lam_r) * (2 + 3 * eta_r))
 
 
-def layered_1d_steady(ny, h, width, eta1, eta2, lam1, lam2, ax, Tc, Th, n=400001):
+def layered_1d_steady(ny, h, width, eta1, eta2, lam1, lam2, ax, Tc, Th, n=400001,
+                      rho1=1.0, rho2=None, tau=None):
     """Steady two-layer channel flow and conduction with the diffuse interface
     of the method: c(y) = 1/2 + 1/2 tanh((y - h)/W) between walls at y = 0 and
     y = ny (fluid 1, c = 0, below), viscosity and conductivity linear in c
     (the reading of the unstated interpolation).  The x-momentum balance
     d/dy(eta u') = -rho a_x with u = 0 on both walls and the heat balance
-    (lam T')' = 0 with T = Tc, Th on the walls are integrated by quadrature
-    (rho = 1):
-        eta u' = -a_x (y - y*),  y* = int(y/eta) / int(1/eta),
+    (lam T')' = 0 with T = Tc, Th on the walls are integrated by quadrature:
+        eta u' = -a_x (R(y) - R*),  R(y) = int_0^y rho,
+        R* = int(R/eta) / int(1/eta)   (u vanishes on both walls),
         T = Tc + (Th - Tc) int_0^y dy/lam / int_0^ny dy/lam.
-    Returns (u, T) at the site centres y = j + 1/2.  The sharp-interface
-    limit (W -> 0) is Eqs. (28)-(29)."""
+    With one density (rho2 None) rho = rho1 throughout.  With two densities
+    rho(c) = rho1 + c (rho2 - rho1), and ``tau`` = (tau_f, tau_T), each a
+    pair for c = 0 and c = 1, gives eta = rho (tau_f(c) - 1/2)/3 and
+    lam = rho cv (tau_T(c) - 1/2)/3 (cv = 1) with tau linear in c; eta1..lam2
+    are then ignored.  Returns (u, T) at the site centres y = j + 1/2.  The
+    sharp-interface limit (W -> 0) with one density is Eqs. (28)-(29)."""
     y = np.linspace(0.0, float(ny), n)
     c = 0.5 + 0.5 * np.tanh((y - h) / width)
-    eta = eta1 + c * (eta2 - eta1)
-    lam = lam1 + c * (lam2 - lam1)
+    rho = rho1 + c * ((rho1 if rho2 is None else rho2) - rho1)
+    if tau is None:
+        eta = eta1 + c * (eta2 - eta1)
+        lam = lam1 + c * (lam2 - lam1)
+    else:
+        (tf0, tf1), (tT0, tT1) = tau
+        eta = rho * (tf0 + c * (tf1 - tf0) - 0.5) / 3.0
+        lam = rho * (tT0 + c * (tT1 - tT0) - 0.5) / 3.0
 
     def cumint(f):
         return np.concatenate([[0.0], np.cumsum(0.5 * (f[1:] + f[:-1]) * np.diff(y))])
 
-    i0, i1, il = cumint(1.0 / eta), cumint(y / eta), cumint(1.0 / lam)
+    R = rho1 * y if rho2 is None else cumint(rho)
+    i0, i1, il = cumint(1.0 / eta), cumint(R / eta), cumint(1.0 / lam)
     u = -ax * (i1 - (i1[-1] / i0[-1]) * i0)
     T = Tc + (Th - Tc) * il / il[-1]
     yc = np.arange(ny) + 0.5

@@ -198,3 +198,47 @@ def test_curvature_force_vanishes_on_flat_profile(oracle_mod):
     ea = d["eps"] * d["alpha"]
     assert a["Fx"] == pytest.approx(ea * gy * gy * (-p["sigmaT"] * gTx), rel=1e-13)
     assert a["Fy"] == 0.0
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_collision_moments_two_densities(oracle_mod, seed):
+    """Two densities, rho(c) = rho1 + c (rho2 - rho1) (the closure the paper
+    leaves open): T = sum hbar / (rho(c) cv) (Eq. 26); the pressure of Eq. 9
+    is p = sum f + (1/2) u.grad(rho cs^2); the density term of Eq. 6,
+    (xi - u).grad(rho cs^2)(Gamma_i(u) - Gamma_i(0)), has zero first moment,
+    and with the pressure's own correction the collision adds exactly
+    cs^2 u.grad rho to sum f; the first moments use the local rho;
+    the g forcing uses F - grad p (Eq. 12) and the hbar forcing F-bar =
+    grad(rho cs^2) - grad p + F (Sec. III)."""
+    rng = np.random.default_rng(100 + seed)
+    p = dict(_random_params(rng), rho2=float(rng.uniform(0.3, 4.0)))
+    pre, st = _random_site(rng)
+    post, a = oracle_mod.collide_site(p, pre, st)
+    f, g, h = pre[:9], pre[9:18], pre[18:]
+    fs, gs, hs = post[:9], post[9:18], post[18:]
+    c = g.sum()
+    rho = p["rho"] + c * (p["rho2"] - p["rho"])
+    cv = p["cv"]
+    grad_rho = (p["rho2"] - p["rho"]) * st[0:2]
+    gradp = st[5:7]
+    T = h.sum() / (rho * cv)
+    assert a["T"] == pytest.approx(T, rel=1e-14)
+    u = np.array([a["ux"], a["uy"]])
+    F = np.array([a["Fx"], a["Fy"]])
+    j = XI.T @ f
+    # u from the f moments with the local density (Eq. 9, reading A1)
+    np.testing.assert_allclose(u, 3 * j / rho + F / (2 * rho), rtol=1e-12, atol=1e-16)
+    assert a["p"] == pytest.approx(f.sum() + 0.5 * CS2 * u @ grad_rho, rel=1e-13, abs=1e-16)
+    wf, wT, wg = a["wf"], a["wT"], a["wg"]
+    assert fs.sum() - f.sum() == pytest.approx(CS2 * u @ grad_rho, rel=1e-9, abs=1e-15)
+    np.testing.assert_allclose(XI.T @ fs, (1 - wf) * j + wf * rho * CS2 * u + (1 - wf / 2) * CS2 * F,
+                               rtol=1e-10, atol=1e-16)
+    np.testing.assert_allclose(
+        XI.T @ gs, (1 - wg) * (XI.T @ g) + wg * c * u + (1 - wg / 2) * c * (F - gradp) / rho,
+        rtol=1e-10, atol=1e-16)
+    Fbar = CS2 * grad_rho - gradp + F
+    np.testing.assert_allclose(
+        XI.T @ hs, (1 - wT) * (XI.T @ h) + wT * rho * cv * T * u + (1 - wT / 2) * cv * T * Fbar,
+        rtol=1e-10, atol=1e-15)
+    assert gs.sum() == pytest.approx(c, rel=1e-12)
+    assert hs.sum() == pytest.approx(h.sum(), rel=1e-12)

@@ -132,6 +132,9 @@ def main():
     ap.add_argument("--precision", default="fp32_dev", choices=("fp32_dev", "fp64"))
     ap.add_argument("--workload", default="multi_droplet")
     ap.add_argument("--diag-every", type=int, default=100)
+    ap.add_argument("--rho2", type=float, default=0.0,
+                    help="density of the c = 1 fluid (two densities, FP64 form; "
+                         "0: one density)")
     ap.add_argument("--csf-form", type=int, default=0, choices=(0, 1),
                     help="capillary part of the CSF force: 0 potential form (default), "
                          "1 curvature form as printed")
@@ -166,7 +169,8 @@ def main():
     if args.adjoint:
         adjoint_bench(args, torch, lbe_csf, wl)
         return
-    w = wl.make(args.workload, csf_form=args.csf_form)
+    extra = {"rho2": args.rho2} if args.rho2 > 0 else {}
+    w = wl.make(args.workload, csf_form=args.csf_form, **extra)
     p = w["params"]
     nx, ny = p["nx"], p["ny"]
     sites = nx * ny
@@ -197,8 +201,13 @@ def main():
     # dominant kernel: the fused step; its average launch time over the timed
     # region (the region also holds steps/diag_every tiny reduction launches)
     bps = BYTES_PER_SITE[args.precision]
+    if args.rho2 > 0:
+        # two densities: the pressure pass reads the 27 FP64 values and writes
+        # the pressure of Eq. 9 (216 + 8 B), which the step then reads (8 B)
+        bps += 216 + 8 + 8
     achieved = bps * sites / (ms_per_step / 1e3) / 1e9
-    traffic = traffic_from_profile(args.workload, args.precision, sites, args.csf_form)
+    traffic = (traffic_from_profile(args.workload, args.precision, sites, args.csf_form)
+               if args.rho2 <= 0 else None)
     out = {
         "metric": "MLUPS (3 coupled D2Q9 lattices)",
         "value": round(mlups, 2),
@@ -215,6 +224,7 @@ def main():
         "config": {"workload": f"{args.workload} {nx}x{ny}", "precision": args.precision,
                    "sites": sites, "diag_every": args.diag_every,
                    "capillary_form": "curvature" if args.csf_form == 1 else "potential",
+                   "densities": [p["rho"], args.rho2] if args.rho2 > 0 else [p["rho"]],
                    "bytes_per_site_update": bps},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),

@@ -17,7 +17,7 @@ __global__ void __launch_bounds__(256)
 init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
             const double *__restrict__ T0, int nx, int ny, int walls_y,
             double beta2, double eps2, double gam3, double rcv, double p0,
-            double Ts, double Tg) {
+            double Ts, double Tg, double rho, double drho, double cv) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= nx || y >= ny) return;
@@ -44,6 +44,8 @@ init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
   const double gmu = gam3 * mu;
   const double T = T0[s];
   const double Tr = Ts + Tg * (y + 0.5);
+  // two densities: rho(c) cv of the site (rcv itself with one density)
+  if (drho != 0.0) rcv = (rho + c * drho) * cv;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const double w = wq<double>(i);

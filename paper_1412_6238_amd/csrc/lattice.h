@@ -27,7 +27,9 @@ enum : int {
   kFields = 2,  // write phi, u, p, T
   kDiag = 4,    // per-block FP64 partial sums of the diagnostics
   kTape = 8,    // write the moments of the source state to the tape
-  kCurv = 16    // capillary force in the curvature form of Eq. 4
+  kCurv = 16,   // capillary force in the curvature form of Eq. 4
+  kVarRho = 32, // two densities, rho(c) = rho + c drho (FP64 form)
+  kPress = 64   // with kVarRho: only the pressure of Eq. 9, into a plane
 };
 
 constexpr int kNumPartials = 7;  // mass, energy, cy, cx, mass_thr, cuy_thr, nonfinite
@@ -54,6 +56,10 @@ struct StepArgs {
   double ax, ay;            // body acceleration
   double p0, Ts, Tg;        // deviation references (FP32 form): w p0 for f,
                             // w rho cv (Ts + Tg y) for hbar at height y
+  double drho;              // rho(c) = rho + c drho (kVarRho)
+  const double *pc;         // kVarRho: the pressure of Eq. 9 of the source
+                            // state, p = sum f + (1/2) u.grad(rho cs^2)
+  double *pc_out;           // kPress: where that pressure is written
   // outputs
   double *phi, *ux, *uy, *p, *T;
   double *partials;         // [gridDim.x][kNumPartials]

@@ -94,9 +94,12 @@ Launch pick_launch(int nx, int ny, bool fp32) {
   return L;
 }
 
+// two fluid densities (rho2 > 0 and different from rho)
+bool two_densities(const lbe_csf_params *p) { return p->rho2 > 0.0 && p->rho2 != p->rho; }
+
 struct Layout {
   size_t state_bytes;
-  size_t off_a, off_b, off_tw, off_part, off_ring, off_cnt, off_rec, off_adj, total;
+  size_t off_a, off_b, off_tw, off_part, off_ring, off_cnt, off_rec, off_pc, off_adj, total;
   AdjLayout adj;
 };
 
@@ -130,6 +133,9 @@ bool params_valid(const lbe_csf_params *p, std::string *why) {
     return bad("non-finite parameter");
   if (p->diag_every < 0) return bad("diag_every must be >= 0");
   if (p->csf_form != 0 && p->csf_form != 1) return bad("csf_form must be 0 or 1");
+  if (!(p->rho2 >= 0.0) || !fin(p->rho2)) return bad("rho2 must be >= 0 (0: one density)");
+  if (two_densities(p) && p->precision != LBE_CSF_FP64)
+    return bad("two densities need the FP64 form");
   return true;
 }
 
@@ -147,6 +153,7 @@ Layout make_layout(const lbe_csf_params *p, int64_t record_steps) {
   L.off_ring = o; o = align_up(o + (size_t)kDiagRing * sizeof(DiagRecord));
   L.off_cnt = o; o = align_up(o + 4 * sizeof(int64_t));
   L.off_rec = o; o = align_up(o + sizeof(DiagRecord));
+  L.off_pc = o; o = align_up(o + (two_densities(p) ? n * 8 : 0));   // pressure of Eq. 9
   L.off_adj = o;
   L.adj = adj_layout(p->nx, p->ny, L.state_bytes, vb, record_steps);
   o = align_up(o + L.adj.total);
@@ -210,6 +217,9 @@ void fill_constants(lbe_csf *h) {
   a.rho = p.rho;
   a.cv = p.cv;
   a.rcv = p.rho * p.cv;
+  a.drho = two_densities(&p) ? p.rho2 - p.rho : 0.0;
+  a.pc = two_densities(&p) ? reinterpret_cast<const double *>(h->ws + h->L.off_pc) : nullptr;
+  a.pc_out = two_densities(&p) ? reinterpret_cast<double *>(h->ws + h->L.off_pc) : nullptr;
   a.tauf0 = p.tau_f[0];
   a.dtauf = p.tau_f[1] - p.tau_f[0];
   a.tauT0 = p.tau_T[0];
@@ -248,10 +258,14 @@ void launch_pipe(const Launch &la, const StepArgs &a, hipStream_t st) {
 
 template <typename S, typename R, bool DEV, int MODE>
 void launch_mode(const Launch &la, const StepArgs &a, hipStream_t st) {
-  switch (la.pipe) {
-    case 0: launch_pipe<S, R, DEV, MODE, 0>(la, a, st); break;
-    case 2: launch_pipe<S, R, DEV, MODE, 2>(la, a, st); break;
-    default: launch_pipe<S, R, DEV, MODE, 1>(la, a, st); break;
+  if constexpr ((MODE & kVarRho) != 0) {
+    launch_pipe<S, R, DEV, MODE, 1>(la, a, st);   // two densities: rows one ahead
+  } else {
+    switch (la.pipe) {
+      case 0: launch_pipe<S, R, DEV, MODE, 0>(la, a, st); break;
+      case 2: launch_pipe<S, R, DEV, MODE, 2>(la, a, st); break;
+      default: launch_pipe<S, R, DEV, MODE, 1>(la, a, st); break;
+    }
   }
 }
 
@@ -268,7 +282,27 @@ void launch_prec(int mode, const Launch &la, const StepArgs &a, hipStream_t st) 
     case kStore | kDiag | kCurv: launch_mode<S, R, DEV, kStore | kDiag | kCurv>(la, a, st); break;
     case kFields | kCurv: launch_mode<S, R, DEV, kFields | kCurv>(la, a, st); break;
     case kDiag | kCurv: launch_mode<S, R, DEV, kDiag | kCurv>(la, a, st); break;
-    default: launch_mode<S, R, DEV, kFields | kDiag>(la, a, st); break;
+    default:
+      if constexpr (!DEV) {
+        // two densities (FP64 form only): the pressure pass, then the step
+        constexpr int V = kVarRho, P = kVarRho | kPress;
+        switch (mode) {
+          case P: launch_mode<S, R, DEV, P>(la, a, st); return;
+          case P | kCurv: launch_mode<S, R, DEV, P | kCurv>(la, a, st); return;
+          case V | kStore: launch_mode<S, R, DEV, V | kStore>(la, a, st); return;
+          case V | kStore | kDiag: launch_mode<S, R, DEV, V | kStore | kDiag>(la, a, st); return;
+          case V | kFields: launch_mode<S, R, DEV, V | kFields>(la, a, st); return;
+          case V | kDiag: launch_mode<S, R, DEV, V | kDiag>(la, a, st); return;
+          case V | kStore | kCurv: launch_mode<S, R, DEV, V | kStore | kCurv>(la, a, st); return;
+          case V | kStore | kDiag | kCurv:
+            launch_mode<S, R, DEV, V | kStore | kDiag | kCurv>(la, a, st); return;
+          case V | kFields | kCurv: launch_mode<S, R, DEV, V | kFields | kCurv>(la, a, st); return;
+          case V | kDiag | kCurv: launch_mode<S, R, DEV, V | kDiag | kCurv>(la, a, st); return;
+          default: break;
+        }
+      }
+      launch_mode<S, R, DEV, kFields | kDiag>(la, a, st);
+      break;
   }
 }
 
@@ -284,6 +318,13 @@ int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
   a.p = p;
   a.T = T;
   if (h->P.csf_form == 1) mode |= kCurv;
+  if (a.drho != 0.0) {
+    // two densities: the pressure of Eq. 9 of the source state first (it
+    // needs u, hence the force, at every site of the stencil)
+    launch_prec<double, double, false>(kVarRho | kPress | (mode & kCurv), h->la, a, h->stream);
+    HIPCHK(h, hipGetLastError());
+    mode |= kVarRho;
+  }
   if (h->P.precision == LBE_CSF_FP64)
     launch_prec<double, double, false>(mode, h->la, a, h->stream);
   else
@@ -495,11 +536,12 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   if (params->precision == LBE_CSF_FP64)
     init_kernel<double, false><<<grid, 256, 0, h->stream>>>(
         static_cast<double *>(h->state[0]), phi0, T0, nx, ny, params->walls_y, beta2, eps2,
-        gam3, h->base.rcv, params->p0, 0.0, 0.0);
+        gam3, h->base.rcv, params->p0, 0.0, 0.0, h->base.rho, h->base.drho, h->base.cv);
   else
     init_kernel<float, true><<<grid, 256, 0, h->stream>>>(
         static_cast<float *>(h->state[0]), phi0, T0, nx, ny, params->walls_y, beta2, eps2,
-        gam3, h->base.rcv, params->p0, params->T_shift, params->T_grad);
+        gam3, h->base.rcv, params->p0, params->T_shift, params->T_grad, h->base.rho, 0.0,
+        h->base.cv);
   e = hipGetLastError();
   if (e != hipSuccess) {
     h->err = std::string("init kernel: ") + hipGetErrorString(e);
@@ -514,6 +556,8 @@ int lbe_csf_step(lbe_csf *h, int64_t nsteps, int32_t record) {
   if (nsteps < 0) return fail(h, LBE_CSF_EINVAL, "nsteps < 0");
   if (record && h->P.csf_form != 0)
     return fail(h, LBE_CSF_EINVAL, "the adjoint covers the potential form (csf_form 0) only");
+  if (record && h->base.drho != 0.0)
+    return fail(h, LBE_CSF_EINVAL, "the adjoint covers one density only");
   if (record && (nsteps == 0 || nsteps > h->record_cap))
     return fail(h, LBE_CSF_EINVAL,
                 "record needs 0 < nsteps <= record_steps of the workspace (" +

@@ -77,10 +77,12 @@ struct RowVals {
   double g0, h0;
 };
 
-// Moments of a loaded site: c (FP64), T or Delta T (FP64), p or Delta p.
-template <typename R>
+// Moments of a loaded site: c (FP64), T or Delta T (FP64), p or Delta p
+// (sum f).  With two densities T = sum hbar / (rho(c) cv).
+template <typename R, bool VR = false>
 __device__ __forceinline__ void site_moments(const RowVals<R> &r, double inv_rcv, double *c,
-                                             double *T, R *p) {
+                                             double *T, R *p, double rho = 0.0,
+                                             double drho = 0.0, double cv = 0.0) {
   R cs = 0, hs = 0, f = 0;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -91,7 +93,10 @@ __device__ __forceinline__ void site_moments(const RowVals<R> &r, double inv_rcv
     }
   }
   *c = r.g0 + double(cs);
-  *T = (r.h0 + double(hs)) * inv_rcv;
+  if (VR)
+    *T = (r.h0 + double(hs)) / ((rho + *c * drho) * cv);
+  else
+    *T = (r.h0 + double(hs)) * inv_rcv;
   *p = f;
 }
 
@@ -104,6 +109,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
                                             const R *tS, const R *tC, const R *tN, const R *pS,
                                             const R *pC, const R *pN, const RowVals<R> &cur,
                                             double *acc) {
+  constexpr bool VR = (MODE & kVarRho) != 0;
   const int nx = a.nx, ny = a.ny;
   const size_t n = (size_t)nx * (size_t)ny;
   // order parameter and its stencils in FP64
@@ -176,19 +182,30 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
   // capillary part along grad c: kcap sigma mu (potential form) or
   // -sigma eps alpha |grad c| div n (curvature form)
   const double ks = (MODE & kCurv) ? -a.epsalpha * sigma * tHt : a.kcap * sigma * mu_d;
-  const double inv_rho = 1.0 / a.rho;
-  const double Fxd = ks * gcx_d + a.epsalpha * (g2 * gsx - gds * gcx_d) + a.rho * a.ax;
-  const double Fyd = ks * gcy_d + a.epsalpha * (g2 * gsy - gds * gcy_d) + a.rho * a.ay;
+  // two densities: rho(c) = rho + c drho, grad rho = drho grad c
+  const double rho_s = VR ? a.rho + cd * a.drho : a.rho;
+  const double grx = VR ? a.drho * gcx_d : 0.0, gry = VR ? a.drho * gcy_d : 0.0;
+  const double inv_rho = 1.0 / rho_s;
+  const double Fxd = ks * gcx_d + a.epsalpha * (g2 * gsx - gds * gcx_d) + rho_s * a.ax;
+  const double Fyd = ks * gcy_d + a.epsalpha * (g2 * gsy - gds * gcy_d) + rho_s * a.ay;
   const double uxd = 3.0 * jxd * inv_rho + 0.5 * Fxd * inv_rho;
   const double uyd = 3.0 * jyd * inv_rho + 0.5 * Fyd * inv_rho;
+  if (MODE & kPress) {
+    // the pressure of Eq. 9: p = sum f + (1/2) u.grad(rho cs^2)
+    a.pc_out[(size_t)j * nx + x] = double(pv) + (0.5 / 3.0) * (uxd * grx + uyd * gry);
+    return;
+  }
   const R ux = R(uxd), uy = R(uyd);
+  // F - grad p drives c (Eq. 12); F-bar = grad(rho cs^2) - grad p + F
+  // drives hbar (Sec. III)
   const R Fbx = R(Fxd - gpx), Fby = R(Fyd - gpy);
+  const R Fhx = VR ? R(Fxd - gpx + grx / 3.0) : Fbx, Fhy = VR ? R(Fyd - gpy + gry / 3.0) : Fby;
 
   if (MODE & kDiag) {
     const double Td = DEV ? double(Tv) + Trow : double(Tv);
     const double yy = double(j) + 0.5, xx = double(x) + 0.5;
     acc[0] += cd;
-    acc[1] += a.rcv * Td;
+    acc[1] += (VR ? rho_s * a.cv : a.rcv) * Td;
     acc[2] += cd * yy;
     acc[3] += cd * xx;
     if (cd >= 0.5) {
@@ -222,14 +239,16 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     double hs = 0.0;
 #pragma unroll
     for (int q = 1; q < 9; ++q) hs += double(cur.v[18 + q]);
-    const double Td = (cur.h0 + hs) / a.rcv;          // T or Delta T, FP64
+    const double rcv_s = VR ? rho_s * a.cv : a.rcv;
+    const double Td = (cur.h0 + hs) / rcv_s;          // T or Delta T, FP64
     const double Tfull_d = DEV ? Td + Trow : Td;
     const R Tfull = R(Tfull_d);
-    const R rcvT = k.rcv * Tfull;
+    const R rcvT = (VR ? R(rcv_s) : k.rcv) * Tfull;
     const R gmu = R(a.gam3 * mu_d);
     const R cgf = R(1) - R(0.5) * wg, chf = R(1) - R(0.5) * wT;
-    const R src_g = R(3) * c * k.inv_rho;     // c / (rho cs^2)
-    const R src_h = R(3) * k.inv_rho;         // 1 / (rho cs^2)
+    const R irho = VR ? R(inv_rho) : k.inv_rho;
+    const R src_g = R(3) * c * irho;          // c / (rho cs^2)
+    const R src_h = R(3) * irho;              // 1 / (rho cs^2)
     const bool walls = a.walls_y != 0;
     const bool bot = walls && j == 0, top = walls && j == ny - 1;
     R gsum = 0;                                // sum of g_1..8 = c - g_0
@@ -252,6 +271,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const R gam = w + G;
       const R cxu = R(kEx[i]) - ux, cyu = R(kEy[i]) - uy;
       const R fbe = Fbx * cxu + Fby * cyu;
+      const R fhe = VR ? Fhx * cxu + Fhy * cyu : fbe;
       // f (Eqs. 6-7): f^eq = w p + rho cs^2 G, in FP64.  Near an interface
       // the forcing term carries the capillary force, which the pressure
       // gradient balances; FP32 weights and Gamma_i would leave a relative
@@ -261,15 +281,21 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const double ed = double(kEx[i]) * uxd + double(kEy[i]) * uyd;
       const double Gd = wd * (3.0 * ed + 4.5 * ed * ed - 1.5 * usqd);
       const double fed = Fxd * (double(kEx[i]) - uxd) + Fyd * (double(kEy[i]) - uyd);
-      const double feqd = wd * double(pv) + a.rho * (1.0 / 3.0) * Gd;
+      const double feqd = wd * double(pv) + rho_s * (1.0 / 3.0) * Gd;
       const double vd = double(cur.v[i]);
-      const R fo = R(vd - wfd * (vd - feqd) + cfd * fed * (wd + Gd));
+      // with two densities the forcing adds (xi - u).grad(rho cs^2)
+      // (Gamma_i(u) - Gamma_i(0)) (Eq. 6); Gamma_i(0) = w_i
+      const double srcf = VR ? fed * (wd + Gd) +
+                                   (1.0 / 3.0) * (grx * (double(kEx[i]) - uxd) +
+                                                  gry * (double(kEy[i]) - uyd)) * Gd
+                             : fed * (wd + Gd);
+      const R fo = R(vd - wfd * (vd - feqd) + cfd * srcf);
       // g (Eqs. 12-14): g^eq_0 = c - (1 - w0) 3 Gamma mu + c G_0,
       //                 g^eq_i = w_i 3 Gamma mu + c G_i
       const R gsrc = cgf * src_g * fbe * gam;
       // hbar (Eqs. 22, 25): h^eq = rho cv T Gamma_i
       const R heq_full = rcvT * gam;
-      const R hsrc = chf * src_h * fbe * heq_full;
+      const R hsrc = chf * src_h * fhe * heq_full;
       if (i == 0) {
         st(0, s_own, fo);
         gsrc0 = gsrc;
@@ -292,7 +318,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
         const R twv = DEV ? R(tw[x] - Trow) : R(tw[x]);
         st(o, s_own, fo);
         st(9 + o, s_own, go);
-        st(18 + o, s_own, R(2) * w * k.rcv * twv - ho);
+        st(18 + o, s_own, R(2) * w * (VR ? R(rcv_s) : k.rcv) * twv - ho);
         dh += cur.v[18 + i] - ho;
       } else {
         int xd = x + kEx[i];
@@ -323,7 +349,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const R w0 = wq<R>(0);
       const R d0 = gsum - (R(1) - w0) * gmu + c * G0;
       gnew = cur.g0 + double(wg * d0 + gsrc0);
-      const double hdiff = cur.h0 - a.rcv * Tfull_d * double(gam0);
+      const double hdiff = cur.h0 - rcv_s * Tfull_d * double(gam0);
       hnew = cur.h0 + double(-wT * R(hdiff) + hsrc0);
     }
     buf_store_nt<double>(gnew, rd, s_own * 8u, dbase);
@@ -440,14 +466,18 @@ step_kernel(const StepArgs a) {
       }
     }
   };
-  auto put_own = [&](int slot, const RowVals<R> &r) {
+  // with two densities (FP64 form) the ring's pressure is that of Eq. 9,
+  // computed by the pressure pass of the same source state
+  constexpr bool VR = (MODE & kVarRho) != 0;
+  constexpr bool VRP = VR && !(MODE & kPress);
+  auto put_own = [&](int slot, const RowVals<R> &r, int row) {
     if (act) {
       double c, T;
       R p;
-      site_moments(r, inv_rcv, &c, &T, &p);
+      site_moments<R, VR>(r, inv_rcv, &c, &T, &p, a.rho, a.drho, a.cv);
       ringc[slot][lane + 1] = c;
       ringt[slot][lane + 1] = R(T);
-      ringp[slot][lane + 1] = p;
+      ringp[slot][lane + 1] = VRP ? R(a.pc[(size_t)row * nx + x]) : p;
     }
   };
   // halo moments from prefetched values (PIPE 2)
@@ -484,7 +514,17 @@ step_kernel(const StepArgs a) {
         R hs = 0;
 #pragma unroll
         for (int q = 1; q < 9; ++q) hs += ld(18 + q, s);
-        ringt[slot][hpos] = R((ldd(1, s) + double(hs)) * inv_rcv);
+        if (VR) {
+          R cs = 0;
+#pragma unroll
+          for (int q = 1; q < 9; ++q) cs += ld(9 + q, s);
+          const double ch = ldd(0, s) + double(cs);
+          ringt[slot][hpos] = R((ldd(1, s) + double(hs)) / ((a.rho + ch * a.drho) * a.cv));
+        } else {
+          ringt[slot][hpos] = R((ldd(1, s) + double(hs)) * inv_rcv);
+        }
+      } else if (VRP) {
+        ringp[slot][hpos] = R(a.pc[(size_t)row * nx + hx]);
       } else {
         R f = 0;
 #pragma unroll
@@ -522,7 +562,7 @@ step_kernel(const StepArgs a) {
       put_ghost(row & 3, adj & 3, row < 0 ? a.twb : a.twt);
     } else {
       load_row(wrap_row(row), tmp);
-      put_own(row & 3, tmp);
+      put_own(row & 3, tmp, wrap_row(row));
       put_halo_direct(row & 3, wrap_row(row));
     }
   };
@@ -537,7 +577,7 @@ step_kernel(const StepArgs a) {
   for (int q = 0; q < 27; ++q) cur.v[q] = nxt.v[q] = R(0);
   cur.g0 = cur.h0 = nxt.g0 = nxt.h0 = 0.0;
   load_row(y0, cur);
-  put_own(y0 & 3, cur);
+  put_own(y0 & 3, cur, y0);
   put_halo_direct(y0 & 3, y0);
   moments_or_ghost(y0 - 1, y0, nxt);
   if (PIPE == 2 && !is_ghost(y0 + 1)) {
@@ -556,7 +596,7 @@ step_kernel(const StepArgs a) {
       if (is_ghost(j + 1)) {
         put_ghost((j + 1) & 3, j & 3, a.twt);
       } else {
-        put_own((j + 1) & 3, nxt);
+        put_own((j + 1) & 3, nxt, wrap_row(j + 1));
         put_halo((j + 1) & 3, hnxt);
       }
       lds_barrier();
@@ -582,6 +622,7 @@ step_kernel(const StepArgs a) {
   }
   if (MODE & kDiag)
     block_partials<NW>(acc, red, lane, a.partials + (size_t)blockIdx.x * kNumPartials);
+  static_assert(!VR || (PIPE == 1 && !DEV), "two densities: FP64 form, rows one ahead");
 }
 
 }  // namespace lbe

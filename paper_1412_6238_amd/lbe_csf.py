@@ -54,6 +54,7 @@ class lbe_csf_params(ctypes.Structure):
         ("force", ctypes.c_double * 2),
         ("p0", ctypes.c_double), ("T_shift", ctypes.c_double), ("T_grad", ctypes.c_double),
         ("diag_every", ctypes.c_int32), ("csf_form", ctypes.c_int32),
+        ("rho2", ctypes.c_double),
     ]
 
 
@@ -123,6 +124,7 @@ def make_params(p: dict, precision="fp64", diag_every=0) -> lbe_csf_params:
     P.p0, P.T_shift = float(p["p0"]), float(p.get("T_shift", 0.0))
     P.T_grad = float(p.get("T_grad", 0.0))
     P.diag_every, P.csf_form = int(diag_every), int(p.get("csf_form", 0))
+    P.rho2 = float(p.get("rho2", 0.0))
     return P
 
 

@@ -11,7 +11,10 @@
  * linear surface tension sigma(T) = sigma0 - sigmaT (T - Tref) (Eq. 5, with
  * sigmaT = -d sigma / dT) and the force
  *   F = kcap sigma mu grad c + eps alpha (|grad c|^2 grad sigma
- *       - (grad c . grad sigma) grad c) + rho a             (Eqs. 3-4).
+ *       - (grad c . grad sigma) grad c) + rho a             (Eqs. 3-4),
+ * whose capillary part may instead take the curvature form of Eq. 4
+ * (csf_form = 1).  With two densities (rho2) rho = rho(c) and the density
+ * terms of Eqs. 6 and 9 and Sec. III enter.
  *
  * Grid: sites (i, j), x = i + 1/2, y = j + 1/2, index j * nx + i (x fastest).
  * x is periodic.  With walls_y = 1 no-slip walls sit halfway, at y = 0 and
@@ -132,6 +135,7 @@ typedef struct lbe_csf lbe_csf; /* opaque host object */
 /* Bytes of device workspace needed for these parameters.  record_steps > 0
  * reserves room for lbe_csf_backward after a recorded run of that many steps
  * (ceil(sqrt(N)) spaced checkpoints plus one segment of replay states).
+ * Two densities add one FP64 plane of nx*ny (the pressure of Eq. 9).
  * Errors: EINVAL for invalid parameters or NULL bytes. */
 LBE_CSF_API int lbe_csf_workspace_size(const lbe_csf_params *params, int64_t record_steps,
                            size_t *bytes);
@@ -153,7 +157,10 @@ LBE_CSF_API int lbe_csf_create(const lbe_csf_params *params, void *workspace, si
 
 /* Advance nsteps >= 0 steps.  record = 1 keeps ceil(sqrt(N)) checkpoints of
  * this run for lbe_csf_backward (the run must start at the handle's current
- * state and N = nsteps <= record_steps); record = 0 discards any record.
+ * state and N = nsteps <= record_steps; the adjoint covers the potential
+ * form with one density, so record = 1 is EINVAL with csf_form = 1 or two
+ * densities); record = 0 discards any record.  With two densities every
+ * step is two launches: the pressure of Eq. 9, then the step.
  * With diag_every > 0 the diagnostics of F_n for every n divisible by
  * diag_every in [start, start + nsteps) are computed inside the step kernel
  * and this call synchronises once at its end to check them: ENONFINITE if any

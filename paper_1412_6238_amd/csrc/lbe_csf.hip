@@ -9,6 +9,7 @@
 //   diag ring            4096 records of (step, 7 sums)
 //   counters             records written, non-finite total
 //   one record           target of synchronous diagnostics
+//   pressure plane       nx * ny FP64, with two densities only (Eq. 9)
 //   adjoint region       present when record_steps > 0 (see adjoint.h)
 #include <hip/hip_runtime.h>
 

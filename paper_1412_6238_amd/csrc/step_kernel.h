@@ -28,12 +28,19 @@
 // Work decomposition: a block owns a strip of 64*NW columns and marches up a
 // chunk of rows, one column per lane.  The moments a row's stencils need
 // (c, T, p) sit in an LDS ring of four rows, filled one row ahead of the row
-// being collided; helper lanes add the halo column on each side.  PIPE 1
-// keeps the next row's values in registers, loaded one row ahead of the
-// collision; PIPE 0 loads a row twice (for the moments and again, from
-// cache, for the collision).
-// Either way every distribution is read from HBM once per step (halo columns
-// and the two boundary rows of a chunk are re-read from cache).
+// being collided; helper lanes add the halo column on each side.  PIPE 2
+// issues the loads of a row two rows ahead of its collision and keeps two
+// rows in registers; PIPE 1 keeps the next row's values in registers,
+// loaded one row ahead of the collision; PIPE 0 loads a row twice (for the
+// moments and again, from cache, for the collision).
+// Every distribution is read from HBM once per step (halo columns and the
+// two boundary rows of a chunk are read again by the neighbouring block).
+//
+// Mode bits (template MODE): kStore (collide and stream), kDiag (FP64
+// diagnostic partials), kFields (macroscopic output), kTape (moments for the
+// adjoint), kCurv (capillary force in the curvature form of Eq. 4), kVarRho
+// (two densities; the ring then holds the pressure of Eq. 9, which a
+// kVarRho | kPress launch of the same kernel writes first).
 //
 // Two arithmetic forms share the templates:
 //   R = double, DEV = false: FP64 values as defined by the paper;

@@ -93,7 +93,8 @@ typedef struct {
   double T_grad;         /* temperature T_ref(y) = T_shift + T_grad y (a
                             background close to the expected field, such as
                             the conduction profile between the walls, keeps
-                            the stored deviations and their rounding small)  */
+                            the stored deviations and their rounding small);
+                            must be 0 with walls_y = 0 (not periodic)        */
   int32_t diag_every;    /* > 0: diagnostics of every diag_every-th state
                             during lbe_csf_step (kept on the device, fetched
                             by lbe_csf_diag_history); 0: none               */

@@ -404,9 +404,9 @@ adj_collide_kernel(const AdjArgs aa) {
     const __amdgpu_buffer_rsrc_t wd = plane_rsrc(aa.d_out, 27 * n * sizeof(R));
     const __amdgpu_buffer_rsrc_t wa = plane_rsrc(aa.a, 7 * n * sizeof(R));
 #pragma unroll
-    for (int q = 0; q < 27; ++q) buf_store_nt<R>(db[q], wd, s * (uint32_t)sizeof(R), (uint32_t)q * pb);
+    for (int q = 0; q < 27; ++q) buf_store<R>(db[q], wd, s * (uint32_t)sizeof(R), (uint32_t)q * pb);
 #pragma unroll
-    for (int m = 0; m < 7; ++m) buf_store_nt<R>(da[m], wa, s * (uint32_t)sizeof(R), (uint32_t)m * pb);
+    for (int m = 0; m < 7; ++m) buf_store<R>(da[m], wa, s * (uint32_t)sizeof(R), (uint32_t)m * pb);
   }
   // dJ/dsigmaT: deterministic block sum, accumulated over the steps
   {
@@ -500,9 +500,9 @@ adj_stencil_kernel(const AdjArgs aa) {
   }
   const uint32_t s = (uint32_t)(y * nx + x);
   const __amdgpu_buffer_rsrc_t wm = plane_rsrc(aa.m_out, 3 * n * sizeof(R));
-  buf_store_nt<R>(pbv, wm, s * (uint32_t)sizeof(R), 0u);
-  buf_store_nt<R>(cb, wm, s * (uint32_t)sizeof(R), pb);
-  buf_store_nt<R>(Tb * R(1.0 / a.rcv), wm, s * (uint32_t)sizeof(R), 2 * pb);
+  buf_store<R>(pbv, wm, s * (uint32_t)sizeof(R), 0u);
+  buf_store<R>(cb, wm, s * (uint32_t)sizeof(R), pb);
+  buf_store<R>(Tb * R(1.0 / a.rcv), wm, s * (uint32_t)sizeof(R), 2 * pb);
 }
 
 // lambda_N from the seed on c = sum_q g_q: D = the seed on each g_q, M = 0.

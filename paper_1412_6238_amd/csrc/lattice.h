@@ -97,7 +97,7 @@ __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_of
 // (shifted, partially overlapping) row stores non-temporal made the step
 // slower, because neighbouring waves' partial lines then reach HBM unmerged.
 template <typename T>
-__device__ __forceinline__ void buf_store_nt(T v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off,
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off,
                                              uint32_t base = 0) {
   if constexpr (sizeof(T) == 4) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)byte_off,

@@ -137,6 +137,11 @@ bool params_valid(const lbe_csf_params *p, std::string *why) {
   if (!(p->rho2 >= 0.0) || !fin(p->rho2)) return bad("rho2 must be >= 0 (0: one density)");
   if (two_densities(p) && p->precision != LBE_CSF_FP64)
     return bad("two densities need the FP64 form");
+  // the FP32 form's linear thermal reference T_shift + T_grad y is not
+  // periodic: a population crossing a periodic y boundary would change
+  // reference by T_grad ny instead of T_grad
+  if (p->precision == LBE_CSF_FP32_DEV && p->walls_y == 0 && p->T_grad != 0.0)
+    return bad("T_grad must be 0 with periodic y in the FP32 form");
   return true;
 }
 

@@ -67,13 +67,12 @@ __host__ __device__ constexpr int plane_of(int q) { return q < 9 ? q : (q < 18 ?
 template <typename R>
 struct Consts {
   R rho, inv_rho, rcv, tauf0, dtauf, tauT0, dtauT, wg, gam3, kcap, epsalpha;
-  R sigma0, sigmaT, Tref, bfx, bfy;
+  R sigma0, sigmaT, bfx, bfy;
   __device__ explicit Consts(const StepArgs &a)
       : rho(R(a.rho)), inv_rho(R(1.0 / a.rho)), rcv(R(a.rcv)), tauf0(R(a.tauf0)),
         dtauf(R(a.dtauf)), tauT0(R(a.tauT0)), dtauT(R(a.dtauT)), wg(R(a.omg_g)),
         gam3(R(a.gam3)), kcap(R(a.kcap)), epsalpha(R(a.epsalpha)), sigma0(R(a.sigma0)),
-        sigmaT(R(a.sigmaT)), Tref(R(a.Tref)),
-        bfx(R(a.rho * a.ax)), bfy(R(a.rho * a.ay)) {}
+        sigmaT(R(a.sigmaT)), bfx(R(a.rho * a.ax)), bfy(R(a.rho * a.ay)) {}
 };
 
 // One row of a lane's column: v[q] for the 25 storage planes (v[9], v[18]
@@ -263,7 +262,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     for (int q = 1; q < 9; ++q) gsum += cur.v[9 + q];
     const uint32_t s_own = (uint32_t)(j * nx + x);
     auto st = [&](int q, uint32_t off, R val) {
-      buf_store_nt<S>(S(val), rd, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes);
+      buf_store<S>(S(val), rd, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes);
     };
     // FP32 form: what the eight moving populations of g and hbar give away in
     // this collision, as stored (sum of old - new, each difference of two
@@ -359,8 +358,8 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const double hdiff = cur.h0 - rcv_s * Tfull_d * double(gam0);
       hnew = cur.h0 + double(-wT * R(hdiff) + hsrc0);
     }
-    buf_store_nt<double>(gnew, rd, s_own * 8u, dbase);
-    buf_store_nt<double>(hnew, rd, s_own * 8u, dbase + (uint32_t)(n * 8));
+    buf_store<double>(gnew, rd, s_own * 8u, dbase);
+    buf_store<double>(hnew, rd, s_own * 8u, dbase + (uint32_t)(n * 8));
   }
 }
 

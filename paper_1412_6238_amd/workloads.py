@@ -355,7 +355,8 @@ def random_case(nx, ny, seed, walls_y=1, n_drops=2, amp_T=0.5, **kw):
         sigma0=float(rng.uniform(5e-3, 2e-2)), sigmaT=float(rng.uniform(-2e-3, 2e-3)),
         Tref=float(rng.uniform(0.5, 1.5)),
         force=tuple(rng.uniform(-1e-4, 1e-4, 2)), p0=0.0, T_shift=1.0,
-        T_grad=float(np.random.default_rng(seed + 100003).uniform(-0.02, 0.02)))
+        T_grad=(float(np.random.default_rng(seed + 100003).uniform(-0.02, 0.02))
+                if walls_y else 0.0))
     p.update(kw)
     drops = []
     for _ in range(n_drops):

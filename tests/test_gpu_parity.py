@@ -91,6 +91,27 @@ def test_fp64_initial_state_and_steps(lbe, oracle_mod, nx, ny, walls):
         _cmp(_fields_np(sim), orc.fields(), what=f"fields after +{n}")
 
 
+@pytest.mark.parametrize("nx,ny,walls", [(3, 3, 1), (3, 5, 0), (4, 3, 1), (65, 3, 1), (3, 70, 1)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
+def test_smallest_grids(lbe, oracle_mod, nx, ny, walls, precision):
+    """Degenerate shapes: three columns (the halo columns wrap onto the
+    strip's own sites), three rows between two walls (every row touches a
+    wall), one column past a full wave.  FP64 against the oracle at 1e-12,
+    FP32 deviations at 1e-5."""
+    case = wl.random_case(nx, ny, seed=900 + 7 * nx + ny, walls_y=walls, n_drops=1)
+    _say(f"case smallest grid {nx}x{ny} walls={walls} {precision}")
+    p = case["params"]
+    sim = lbe.Simulation(p, case["phi0"], case["T0"], case["Twall_bot"], case["Twall_top"],
+                         precision=precision)
+    orc = oracle_mod.Oracle(p, case["Twall_bot"], case["Twall_top"]).init(case["phi0"], case["T0"])
+    sim.step(7)
+    orc.step(7)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    _cmp(_fields_np(sim), orc.fields(), tol=tol, what="fields")
+    if precision == "fp64":
+        _cmp({"F": sim.get_state().cpu().numpy()}, {"F": orc.state()}, what="F")
+
+
 @pytest.mark.parametrize("nx,ny,walls", GRIDS[:6])
 def test_fp64_random_state(lbe, oracle_mod, nx, ny, walls):
     """Arbitrary non-equilibrium states, loaded through set_state."""

@@ -259,3 +259,25 @@ def test_e3_curvature_form_at_printed_mobility(lbe):
     win, vc = _migration(lbe, w, nsteps=60000)
     _say("  u_r/U_YGB per t_r " + " ".join(f"{v:.3f}" for v in win) + f"  centroid {vc:.3f}")
     assert max(win) < 0 and vc < 0
+
+
+@pytest.mark.parametrize("name,kw", [("e1", dict(lam_r=10, h_r=1.0)), ("e2", dict(lam_r=1.0)),
+                                     ("e2", dict(lam_r=1.0, csf_form=1)), ("e3", {})])
+def test_paper_cases_fp32_matches_fp64(lbe, name, kw):
+    """The FP32 deviation form against the FP64 path over the full runs of
+    the paper's cases (500,000 / 37,500 / 200,000 steps): relative L2 on phi,
+    u and T within 1e-4."""
+    w = wl.paper_case(name, **kw)
+    _say(f"case paper {name} {kw} fp32_dev vs fp64, {w['nsteps']} steps")
+    res = {}
+    for prec in ("fp64", "fp32_dev"):
+        sim = _sim(lbe, w, precision=prec)
+        sim.step(w["nsteps"])
+        res[prec] = _fields(sim)
+        del sim
+    a, b = res["fp32_dev"], res["fp64"]
+    e = dict(phi=_rel(a["phi"], b["phi"]),
+             u=_rel(np.stack([a["ux"], a["uy"]]), np.stack([b["ux"], b["uy"]])),
+             T=_rel(a["T"], b["T"]))
+    _say("  " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    assert max(e.values()) <= 1e-4

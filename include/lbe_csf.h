@@ -100,8 +100,7 @@ typedef struct {
                             by lbe_csf_diag_history); 0: none               */
   int32_t csf_form;      /* capillary part of the CSF force (Eq. 4):
                             0: potential form kcap sigma mu grad c (exact on
-                               the equilibrium profile; the adjoint covers
-                               this form only);
+                               the equilibrium profile);
                             1: curvature form -sigma (div n) n delta as
                                printed, with n = grad c/|grad c| and
                                delta = eps alpha |grad c|^2, evaluated as
@@ -158,9 +157,9 @@ LBE_CSF_API int lbe_csf_create(const lbe_csf_params *params, void *workspace, si
 
 /* Advance nsteps >= 0 steps.  record = 1 keeps ceil(sqrt(N)) checkpoints of
  * this run for lbe_csf_backward (the run must start at the handle's current
- * state and N = nsteps <= record_steps; the adjoint covers the potential
- * form with one density, so record = 1 is EINVAL with csf_form = 1 or two
- * densities); record = 0 discards any record.  With two densities every
+ * state and N = nsteps <= record_steps; the adjoint covers both force
+ * forms with one density, so record = 1 is EINVAL with two densities);
+ * record = 0 discards any record.  With two densities every
  * step is two launches: the pressure of Eq. 9, then the step.
  * With diag_every > 0 the diagnostics of F_n for every n divisible by
  * diag_every in [start, start + nsteps) are computed inside the step kernel

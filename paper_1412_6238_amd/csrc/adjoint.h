@@ -40,6 +40,9 @@ namespace lbe {
 
 constexpr int kAdjTX = 64;   // adjoint tile: 64 columns x 4 rows, one site per thread
 constexpr int kAdjTY = 4;
+// stencil cotangent planes: grad c, lap c, grad T, grad p, and the Hessian of
+// c (hxx, hxy, hyy; read by the curvature form only)
+constexpr int kAdjA = 10;
 
 struct AdjLayout {
   int64_t record_steps;   // capacity N
@@ -50,7 +53,7 @@ struct AdjLayout {
   size_t plane_bytes;     // one plane of the arithmetic type
   size_t off_chk;         // nchk states
   size_t off_tape;        // K states, then K moment sets
-  size_t off_lam;         // D x2 (27 planes), M x2 (3 planes), A (7 planes)
+  size_t off_lam;         // D x2 (27 planes), M x2 (3 planes), A (kAdjA planes)
   size_t off_part;        // per-block FP64 partial sums of dJ/dsigmaT
   size_t off_tw;          // FP64 [2][nx] dJ/dTwall accumulators
   size_t off_out;         // FP64 scalar result
@@ -83,7 +86,7 @@ inline AdjLayout adj_layout(int nx, int ny, size_t state_bytes, size_t value_byt
   size_t o = 0;
   A.off_chk = o; o += (size_t)A.nchk * A.state_bytes;
   A.off_tape = o; o += (size_t)A.K * (A.state_bytes + A.mom_bytes);
-  A.off_lam = o; o += (2 * 27 + 2 * 3 + 7) * A.plane_bytes;
+  A.off_lam = o; o += (2 * 27 + 2 * 3 + kAdjA) * A.plane_bytes;
   A.off_part = o; o += al((size_t)adj_tiles_x(nx) * adj_tiles_y(ny) * sizeof(double));
   A.off_tw = o; o += al(2 * (size_t)nx * sizeof(double));
   A.off_out = o; o += 256;
@@ -103,7 +106,7 @@ struct AdjArgs {
   const void *d_in;    // D_{n+1}: 27 planes of R
   const void *m_in;    // M_{n+1}: 3 planes of R (f, g, hbar groups)
   void *d_out;         // D_n
-  void *a;             // A_n: 7 planes of R (collide writes, stencil reads)
+  void *a;             // A_n: kAdjA planes of R (collide writes, stencil reads)
   void *m_out;         // M_n
   double *part;        // [tiles] dJ/dsigmaT partials, accumulated over steps
   double *dtw;         // [2][nx] dJ/dT_wall (bottom, top), accumulated
@@ -116,17 +119,18 @@ struct AdjArgs {
 // and, when the relaxation times vary with c (VARTAU), its populations.
 // Outputs: db, the cotangents of the 27 populations through this site's
 // collision (including the paths through its own moments c, T, p, j); da, the
-// cotangents of the seven stencil values (gcx, gcy, lapc, gTx, gTy, gpx, gpy),
-// which the stencil transpose hands on to the neighbours' moments; and
+// cotangents of the stencil values (gcx, gcy, lapc, gTx, gTy, gpx, gpy, and
+// with CURV the Hessian hxx, hxy, hyy of the curvature form), which the
+// stencil transpose hands on to the neighbours' moments; and
 // *dsT += dJ/dsigmaT.  The arithmetic differentiated is site_update's.  With
 // constant relaxation times the populations enter the collision only through
 // the moments, so the moments suffice.
-template <typename R, bool DEV, bool VARTAU>
+template <typename R, bool DEV, bool VARTAU, bool CURV>
 __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> &k,
                                              const RowVals<R> &cur, R p, R jx, R jy, double Td,
                                              double Trow, double cd, R gcx, R gcy, R lapc,
-                                             R gTx, R gTy, R gpx, R gpy, const R *lam, R *db,
-                                             R *da, double *dsT) {
+                                             R gTx, R gTy, R gpx, R gpy, R hxx, R hxy, R hyy,
+                                             const R *lam, R *db, R *da, double *dsT) {
   const R third = R(1) / R(3);
   const R c = R(cd);
   const double Tfull_d = DEV ? Td + Trow : Td;
@@ -137,8 +141,12 @@ __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> 
   const R gsx = -k.sigmaT * gTx, gsy = -k.sigmaT * gTy;
   const R g2 = gcx * gcx + gcy * gcy;
   const R gds = gcx * gsx + gcy * gsy;
-  const R ks = k.kcap * sigma * mu;
   const R ea = k.epsalpha;
+  // capillary coefficient along grad c: kcap sigma mu (potential form) or
+  // -sigma eps alpha t.H.t (curvature form, t.H.t = N / |grad c|^2)
+  const R Nh = gcy * gcy * hxx - R(2) * gcx * gcy * hxy + gcx * gcx * hyy;
+  const R tHt = (CURV && g2 > R(0)) ? Nh / g2 : R(0);
+  const R ks = CURV ? -sigma * ea * tHt : k.kcap * sigma * mu;
   const R Fx = ks * gcx + ea * (g2 * gsx - gds * gcx) + k.bfx;
   const R Fy = ks * gcy + ea * (g2 * gsy - gds * gcy) + k.bfy;
   const R ux = R(3) * jx * k.inv_rho + R(0.5) * Fx * k.inv_rho;
@@ -240,12 +248,27 @@ __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> 
   const R b_ks = b_Fx * gcx + b_Fy * gcy;
   const R b_g2 = ea * (b_Fx * gsx + b_Fy * gsy);
   const R b_gds = -ea * (b_Fx * gcx + b_Fy * gcy);
-  const R b_gcx = b_Fx * (ks - ea * gds) + b_gds * gsx + R(2) * gcx * b_g2;
-  const R b_gcy = b_Fy * (ks - ea * gds) + b_gds * gsy + R(2) * gcy * b_g2;
+  R b_gcx = b_Fx * (ks - ea * gds) + b_gds * gsx + R(2) * gcx * b_g2;
+  R b_gcy = b_Fy * (ks - ea * gds) + b_gds * gsy + R(2) * gcy * b_g2;
   const R b_gsx = ea * g2 * b_Fx + b_gds * gcx;
   const R b_gsy = ea * g2 * b_Fy + b_gds * gcy;
-  const R b_sigma = b_ks * k.kcap * mu;
-  b_mu += b_ks * k.kcap * sigma;
+  R b_sigma, b_hxx = 0, b_hxy = 0, b_hyy = 0;
+  if (CURV) {
+    // ks = -sigma ea tHt, tHt = N / g2 with N = gy^2 hxx - 2 gx gy hxy + gx^2 hyy
+    b_sigma = -b_ks * ea * tHt;
+    if (g2 > R(0)) {
+      const R b_t = -b_ks * sigma * ea;
+      const R ig2 = R(1) / g2;
+      b_hxx = b_t * gcy * gcy * ig2;
+      b_hyy = b_t * gcx * gcx * ig2;
+      b_hxy = -b_t * R(2) * gcx * gcy * ig2;
+      b_gcx += b_t * ((R(2) * gcx * hyy - R(2) * gcy * hxy) - R(2) * gcx * tHt) * ig2;
+      b_gcy += b_t * ((R(2) * gcy * hxx - R(2) * gcx * hxy) - R(2) * gcy * tHt) * ig2;
+    }
+  } else {
+    b_sigma = b_ks * k.kcap * mu;
+    b_mu += b_ks * k.kcap * sigma;
+  }
   *dsT -= double(gTx) * double(b_gsx) + double(gTy) * double(b_gsy) + double(Tm) * double(b_sigma);
   b_T -= k.sigmaT * b_sigma;
   b_c += b_mu * R(a.beta2 * (6.0 * cd * cd - 6.0 * cd + 1.0));
@@ -264,11 +287,16 @@ __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> 
   da[4] = -k.sigmaT * b_gsy;
   da[5] = b_gpx;
   da[6] = b_gpy;
+  if (CURV) {
+    da[7] = b_hxx;
+    da[8] = b_hxy;
+    da[9] = b_hyy;
+  }
 }
 
 
 // ---- adjoint step, part 1: pull and collision transpose ----------------------
-template <typename R, bool DEV, bool VARTAU>
+template <typename R, bool DEV, bool VARTAU, bool CURV>
 __global__ void __launch_bounds__(kAdjTX * kAdjTY)
 adj_collide_kernel(const AdjArgs aa) {
   constexpr int TW = kAdjTX + 2, TH = kAdjTY + 2;
@@ -361,7 +389,7 @@ adj_collide_kernel(const AdjArgs aa) {
     // linearisation point and stencils, as in the forward step
     const int cx = lx + 1, cy = ly + 1;
     const double cd = lc[cy][cx];
-    double gcx_d, gcy_d, lap_d;
+    double gcx_d, gcy_d, lap_d, hxx_d = 0.0, hxy_d = 0.0, hyy_d = 0.0;
     {
       const double e = lc[cy][cx + 1], w = lc[cy][cx - 1], nn = lc[cy + 1][cx],
                    so = lc[cy - 1][cx];
@@ -369,8 +397,14 @@ adj_collide_kernel(const AdjArgs aa) {
                    se = lc[cy - 1][cx + 1];
       gcx_d = (e - w) * (1.0 / 3.0) + (ne + se - nw - sw) * (1.0 / 12.0);
       gcy_d = (nn - so) * (1.0 / 3.0) + (ne + nw - se - sw) * (1.0 / 12.0);
-      lap_d = (2.0 / 3.0) * ((e - cd) + (w - cd) + (nn - cd) + (so - cd)) +
-              (1.0 / 6.0) * ((ne - cd) + (nw - cd) + (se - cd) + (sw - cd));
+      const double dx2 = (e - cd) + (w - cd), dy2 = (nn - cd) + (so - cd);
+      const double dd = (ne - cd) + (nw - cd) + (se - cd) + (sw - cd);
+      lap_d = (2.0 / 3.0) * (dx2 + dy2) + (1.0 / 6.0) * dd;
+      if (CURV) {
+        hxx_d = (2.0 / 3.0) * dx2 - (1.0 / 3.0) * dy2 + (1.0 / 6.0) * dd;
+        hyy_d = (2.0 / 3.0) * dy2 - (1.0 / 3.0) * dx2 + (1.0 / 6.0) * dd;
+        hxy_d = 0.25 * ((ne - nw) - (se - sw));
+      }
     }
     const R third = R(1) / R(3);
     auto grad = [&](R (*f)[TW], R *gx, R *gy) {
@@ -397,16 +431,18 @@ adj_collide_kernel(const AdjArgs aa) {
       cur.g0 = buf_load<double>(rs, s * 8u, kNumS * pb);
       cur.h0 = buf_load<double>(rs, s * 8u, kNumS * pb + (uint32_t)(n * 8));
     }
-    R db[27], da[7];
-    site_adjoint<R, DEV, VARTAU>(a, k, cur, lp[cy][cx], tape_r[2 * n + s], tape_r[3 * n + s],
-                                 double(lt[cy][cx]), Trow, cd, R(gcx_d), R(gcy_d), R(lap_d),
-                                 gTx, gTy, gpx, gpy, lam, db, da, &ds);
+    constexpr int NA = CURV ? kAdjA : 7;
+    R db[27], da[kAdjA];
+    site_adjoint<R, DEV, VARTAU, CURV>(a, k, cur, lp[cy][cx], tape_r[2 * n + s],
+                                       tape_r[3 * n + s], double(lt[cy][cx]), Trow, cd,
+                                       R(gcx_d), R(gcy_d), R(lap_d), gTx, gTy, gpx, gpy,
+                                       R(hxx_d), R(hxy_d), R(hyy_d), lam, db, da, &ds);
     const __amdgpu_buffer_rsrc_t wd = plane_rsrc(aa.d_out, 27 * n * sizeof(R));
-    const __amdgpu_buffer_rsrc_t wa = plane_rsrc(aa.a, 7 * n * sizeof(R));
+    const __amdgpu_buffer_rsrc_t wa = plane_rsrc(aa.a, kAdjA * n * sizeof(R));
 #pragma unroll
     for (int q = 0; q < 27; ++q) buf_store<R>(db[q], wd, s * (uint32_t)sizeof(R), (uint32_t)q * pb);
 #pragma unroll
-    for (int m = 0; m < 7; ++m) buf_store<R>(da[m], wa, s * (uint32_t)sizeof(R), (uint32_t)m * pb);
+    for (int m = 0; m < NA; ++m) buf_store<R>(da[m], wa, s * (uint32_t)sizeof(R), (uint32_t)m * pb);
   }
   // dJ/dsigmaT: deterministic block sum, accumulated over the steps
   {
@@ -426,11 +462,23 @@ adj_collide_kernel(const AdjArgs aa) {
 }
 
 // ---- adjoint step, part 2: stencil transposes --------------------------------
+// weight of neighbour direction k in the Hessian stencil of c, applied to the
+// cotangents (a_xx, a_xy, a_yy) of the site reading it: w_k (9 xi_x^2 - 3),
+// 9 w_k xi_x xi_y and w_k (9 xi_y^2 - 3)
 template <typename R>
+__device__ __forceinline__ R hess_w(int kk, R axx, R axy, R ayy) {
+  const R wk = wq<R>(kk);
+  const R ex = R(kEx[kk]), ey = R(kEy[kk]);
+  return wk * ((R(9) * ex * ex - R(3)) * axx + R(9) * ex * ey * axy + (R(9) * ey * ey - R(3)) * ayy);
+}
+
+
+template <typename R, bool CURV>
 __global__ void __launch_bounds__(kAdjTX * kAdjTY)
 adj_stencil_kernel(const AdjArgs aa) {
   constexpr int TW = kAdjTX + 2, TH = kAdjTY + 2;
-  __shared__ R la[7][TH][TW];
+  constexpr int NA = CURV ? kAdjA : 7;
+  __shared__ R la[NA][TH][TW];
 
   const StepArgs &a = aa.s;
   const int nx = a.nx, ny = a.ny;
@@ -440,7 +488,7 @@ adj_stencil_kernel(const AdjArgs aa) {
   const int x0 = (tile % aa.ntx) * kAdjTX, y0 = (tile / aa.ntx) * kAdjTY;
   const int tid = threadIdx.x;
   const uint32_t pb = (uint32_t)(n * sizeof(R));
-  const __amdgpu_buffer_rsrc_t ra = plane_rsrc(aa.a, 7 * n * sizeof(R));
+  const __amdgpu_buffer_rsrc_t ra = plane_rsrc(aa.a, kAdjA * n * sizeof(R));
   auto wrapx = [&](int v) {
     v %= nx;
     return v < 0 ? v + nx : v;
@@ -455,11 +503,11 @@ adj_stencil_kernel(const AdjArgs aa) {
     const int row = y0 - 1 + r;
     if (ghost(row)) {
 #pragma unroll
-      for (int m = 0; m < 7; ++m) la[m][r][q] = R(0);   // no stencil at a ghost site
+      for (int m = 0; m < NA; ++m) la[m][r][q] = R(0);   // no stencil at a ghost site
     } else {
       const uint32_t s = (uint32_t)(wrapy(row) * nx + wrapx(x0 - 1 + q));
 #pragma unroll
-      for (int m = 0; m < 7; ++m) la[m][r][q] = buf_load<R>(ra, s * (uint32_t)sizeof(R), (uint32_t)m * pb);
+      for (int m = 0; m < NA; ++m) la[m][r][q] = buf_load<R>(ra, s * (uint32_t)sizeof(R), (uint32_t)m * pb);
     }
   }
   __syncthreads();
@@ -477,8 +525,10 @@ adj_stencil_kernel(const AdjArgs aa) {
     cb += gx * la[0][r][q] + gy * la[1][r][q] + R(6) * wk * la[2][r][q];
     Tb += gx * la[3][r][q] + gy * la[4][r][q];
     pbv += gx * la[5][r][q] + gy * la[6][r][q];
+    if constexpr (CURV) cb += hess_w(kk, la[7][r][q], la[8][r][q], la[9][r][q]);
   }
   cb -= R(10.0 / 3.0) * la[2][cy][cx];   // centre weight of the Laplacian
+  if constexpr (CURV) cb -= R(4.0 / 3.0) * (la[7][cy][cx] + la[9][cy][cx]);   // of hxx, hyy
   // wall rows: a site x of the same row whose stencil direction k points into
   // the ghost row reads the mirror image of x + xi_k, which is y
   if (walls && (y == 0 || y == ny - 1)) {
@@ -491,6 +541,7 @@ adj_stencil_kernel(const AdjArgs aa) {
       const R wk = wq<R>(kk);
       const R gx = R(3) * wk * R(kEx[kk]), gy = R(3) * wk * R(kEy[kk]);
       cb += gx * la[0][cy][q] + gy * la[1][cy][q] + R(6) * wk * la[2][cy][q];
+      if constexpr (CURV) cb += hess_w(kk, la[7][cy][q], la[8][cy][q], la[9][cy][q]);
       pbv += gx * la[5][cy][q] + gy * la[6][cy][q];
       const R tg = gx * la[3][cy][q] + gy * la[4][cy][q];
       Tb -= tg;

@@ -288,6 +288,8 @@ void launch_prec(int mode, const Launch &la, const StepArgs &a, hipStream_t st) 
     case kStore | kDiag | kCurv: launch_mode<S, R, DEV, kStore | kDiag | kCurv>(la, a, st); break;
     case kFields | kCurv: launch_mode<S, R, DEV, kFields | kCurv>(la, a, st); break;
     case kDiag | kCurv: launch_mode<S, R, DEV, kDiag | kCurv>(la, a, st); break;
+    case kStore | kTape | kCurv: launch_mode<S, R, DEV, kStore | kTape | kCurv>(la, a, st); break;
+    case kTape | kCurv: launch_mode<S, R, DEV, kTape | kCurv>(la, a, st); break;
     default:
       if constexpr (!DEV) {
         // two densities (FP64 form only): the pressure pass, then the step
@@ -351,11 +353,11 @@ int launch_reduce(lbe_csf *h, int64_t step, bool append) {
 }
 
 // One adjoint step: collision transpose, then stencil transpose.
-template <typename R, bool DEV>
+template <typename R, bool DEV, bool CURV>
 void launch_adj(bool vartau, const AdjArgs &aa, int nblocks, hipStream_t st) {
-  if (vartau) adj_collide_kernel<R, DEV, true><<<nblocks, kAdjTX * kAdjTY, 0, st>>>(aa);
-  else adj_collide_kernel<R, DEV, false><<<nblocks, kAdjTX * kAdjTY, 0, st>>>(aa);
-  adj_stencil_kernel<R><<<nblocks, kAdjTX * kAdjTY, 0, st>>>(aa);
+  if (vartau) adj_collide_kernel<R, DEV, true, CURV><<<nblocks, kAdjTX * kAdjTY, 0, st>>>(aa);
+  else adj_collide_kernel<R, DEV, false, CURV><<<nblocks, kAdjTX * kAdjTY, 0, st>>>(aa);
+  adj_stencil_kernel<R, CURV><<<nblocks, kAdjTX * kAdjTY, 0, st>>>(aa);
 }
 
 // Reverse sweep over the recorded run: for each segment, last first, replay
@@ -426,8 +428,14 @@ int run_backward(lbe_csf *h, const double *dJdc, double *dsT, double *dTw, doubl
       aa.m_in = M[cur];
       aa.d_out = D[1 - cur];
       aa.m_out = M[1 - cur];
-      if (f64) launch_adj<double, false>(vartau, aa, nb, st);
-      else launch_adj<float, true>(vartau, aa, nb, st);
+      const bool curv = h->P.csf_form == 1;
+      if (f64) {
+        if (curv) launch_adj<double, false, true>(vartau, aa, nb, st);
+        else launch_adj<double, false, false>(vartau, aa, nb, st);
+      } else {
+        if (curv) launch_adj<float, true, true>(vartau, aa, nb, st);
+        else launch_adj<float, true, false>(vartau, aa, nb, st);
+      }
       HIPCHK(h, hipGetLastError());
       cur = 1 - cur;
     }
@@ -560,8 +568,6 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
 int lbe_csf_step(lbe_csf *h, int64_t nsteps, int32_t record) {
   if (!h) return LBE_CSF_EINVAL;
   if (nsteps < 0) return fail(h, LBE_CSF_EINVAL, "nsteps < 0");
-  if (record && h->P.csf_form != 0)
-    return fail(h, LBE_CSF_EINVAL, "the adjoint covers the potential form (csf_form 0) only");
   if (record && h->base.drho != 0.0)
     return fail(h, LBE_CSF_EINVAL, "the adjoint covers one density only");
   if (record && (nsteps == 0 || nsteps > h->record_cap))

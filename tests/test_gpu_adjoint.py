@@ -79,6 +79,11 @@ CASES = [
     (130, 13, 1, 11, 10, "fp64", CONST_TAU),
     (70, 9, 0, 7, 12, "fp64", CONST_TAU),
     (130, 13, 1, 11, 10, "fp32_dev", CONST_TAU),
+    # the capillary force in the curvature form (Eq. 4)
+    (37, 21, 1, 5, 12, "fp64", dict(csf_form=1)),
+    (70, 9, 0, 7, 12, "fp64", dict(csf_form=1)),
+    (130, 13, 1, 11, 10, "fp32_dev", dict(csf_form=1)),
+    (130, 13, 1, 11, 10, "fp64", dict(CONST_TAU, csf_form=1)),
 ]
 
 

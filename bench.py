@@ -130,7 +130,10 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="fp32_dev", choices=("fp32_dev", "fp64"))
-    ap.add_argument("--workload", default="multi_droplet")
+    ap.add_argument("--workload", default="multi_droplet",
+                    help="a named synthetic workload (poiseuille, planar_marangoni, droplet, "
+                         "adjoint_droplet, multi_droplet, multi_droplet_slab) or one of the "
+                         "paper's cases (paper_e1, paper_e2, paper_e3)")
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--rho2", type=float, default=0.0,
                     help="density of the c = 1 fluid (two densities, FP64 form; "
@@ -170,7 +173,11 @@ def main():
         adjoint_bench(args, torch, lbe_csf, wl)
         return
     extra = {"rho2": args.rho2} if args.rho2 > 0 else {}
-    w = wl.make(args.workload, csf_form=args.csf_form, **extra)
+    if args.workload.startswith("paper_"):
+        # the paper's own cases of Sec. IV at their printed sizes
+        w = wl.paper_case(args.workload[len("paper_"):], csf_form=args.csf_form, **extra)
+    else:
+        w = wl.make(args.workload, csf_form=args.csf_form, **extra)
     p = w["params"]
     nx, ny = p["nx"], p["ny"]
     sites = nx * ny

@@ -136,8 +136,7 @@ def main():
                          "paper's cases (paper_e1, paper_e2, paper_e3)")
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--rho2", type=float, default=0.0,
-                    help="density of the c = 1 fluid (two densities, FP64 form; "
-                         "0: one density)")
+                    help="density of the c = 1 fluid (two densities; 0: one density)")
     ap.add_argument("--csf-form", type=int, default=0, choices=(0, 1),
                     help="capillary part of the CSF force: 0 potential form (default), "
                          "1 curvature form as printed")
@@ -209,9 +208,10 @@ def main():
     # region (the region also holds steps/diag_every tiny reduction launches)
     bps = BYTES_PER_SITE[args.precision]
     if args.rho2 > 0:
-        # two densities: the pressure pass reads the 27 FP64 values and writes
-        # the pressure of Eq. 9 (216 + 8 B), which the step then reads (8 B)
-        bps += 216 + 8 + 8
+        # two densities: the pressure pass reads the 27 values (216 B in FP64,
+        # 116 B in the FP32 form) and writes the FP64 pressure of Eq. 9 (8 B),
+        # which the step then reads (8 B)
+        bps += bps // 2 + 8 + 8
     achieved = bps * sites / (ms_per_step / 1e3) / 1e9
     traffic = (traffic_from_profile(args.workload, args.precision, sites, args.csf_form)
                if args.rho2 <= 0 else None)

@@ -108,12 +108,15 @@ typedef struct {
                                tangent, H the nine-point Hessian of c)      */
   double rho2;           /* density of the c = 1 fluid; rho above is that of
                             the c = 0 fluid.  0 (or rho2 == rho): one
-                            density.  Two densities (FP64 form only; no
+                            density.  Two densities (both precisions; no
                             adjoint) make rho(c) = rho + c (rho2 - rho) and
                             bring in the density terms of Eq. 6, the
                             pressure p = sum f + (1/2) u.grad(rho cs^2) of
                             Eq. 9 (an extra pass per step and an FP64
-                            plane of workspace) and F-bar of Sec. III     */
+                            plane of workspace) and F-bar of Sec. III.  The
+                            FP32 form keeps its hbar deviations relative to
+                            w rho cv (T_shift + T_grad y) with the rho of
+                            the c = 0 fluid                               */
 } lbe_csf_params;
 
 /* Global diagnostics of a state F_n (FP64 sums; u_r of Sec. IV C). */

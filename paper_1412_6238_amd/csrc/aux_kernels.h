@@ -44,13 +44,15 @@ init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
   const double gmu = gam3 * mu;
   const double T = T0[s];
   const double Tr = Ts + Tg * (y + 0.5);
-  // two densities: rho(c) cv of the site (rcv itself with one density)
-  if (drho != 0.0) rcv = (rho + c * drho) * cv;
+  // two densities: rho(c) cv of the site (rcv itself with one density); the
+  // FP32 form's reference keeps the density of the c = 0 fluid
+  const double rcv_s = drho != 0.0 ? (rho + c * drho) * cv : rcv;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const double w = wq<double>(i);
     F[plane_of(i) * n + s] = DEV ? S(0) : S(w * p0);
-    const double hv = DEV ? w * rcv * (T - Tr) : w * rcv * T;
+    const double hv = DEV ? (drho != 0.0 ? w * (rcv_s * T - rcv * Tr) : w * rcv * (T - Tr))
+                          : w * rcv_s * T;
     if (i == 0) {
       Fd[s] = c - (1.0 - w) * gmu;
       Fd[n + s] = hv;

@@ -138,8 +138,6 @@ bool params_valid(const lbe_csf_params *p, std::string *why) {
   if (p->diag_every < 0) return bad("diag_every must be >= 0");
   if (p->csf_form != 0 && p->csf_form != 1) return bad("csf_form must be 0 or 1");
   if (!(p->rho2 >= 0.0) || !fin(p->rho2)) return bad("rho2 must be >= 0 (0: one density)");
-  if (two_densities(p) && p->precision != LBE_CSF_FP64)
-    return bad("two densities need the FP64 form");
   // the FP32 form's linear thermal reference T_shift + T_grad y is not
   // periodic: a population crossing a periodic y boundary would change
   // reference by T_grad ny instead of T_grad
@@ -293,27 +291,26 @@ void launch_prec(int mode, const Launch &la, const StepArgs &a, hipStream_t st) 
     case kDiag | kCurv: launch_mode<S, R, DEV, kDiag | kCurv>(la, a, st); break;
     case kStore | kTape | kCurv: launch_mode<S, R, DEV, kStore | kTape | kCurv>(la, a, st); break;
     case kTape | kCurv: launch_mode<S, R, DEV, kTape | kCurv>(la, a, st); break;
-    default:
-      if constexpr (!DEV) {
-        // two densities (FP64 form only): the pressure pass, then the step
-        constexpr int V = kVarRho, P = kVarRho | kPress;
-        switch (mode) {
-          case P: launch_mode<S, R, DEV, P>(la, a, st); return;
-          case P | kCurv: launch_mode<S, R, DEV, P | kCurv>(la, a, st); return;
-          case V | kStore: launch_mode<S, R, DEV, V | kStore>(la, a, st); return;
-          case V | kStore | kDiag: launch_mode<S, R, DEV, V | kStore | kDiag>(la, a, st); return;
-          case V | kFields: launch_mode<S, R, DEV, V | kFields>(la, a, st); return;
-          case V | kDiag: launch_mode<S, R, DEV, V | kDiag>(la, a, st); return;
-          case V | kStore | kCurv: launch_mode<S, R, DEV, V | kStore | kCurv>(la, a, st); return;
-          case V | kStore | kDiag | kCurv:
-            launch_mode<S, R, DEV, V | kStore | kDiag | kCurv>(la, a, st); return;
-          case V | kFields | kCurv: launch_mode<S, R, DEV, V | kFields | kCurv>(la, a, st); return;
-          case V | kDiag | kCurv: launch_mode<S, R, DEV, V | kDiag | kCurv>(la, a, st); return;
-          default: break;
-        }
+    default: {
+      // two densities: the pressure pass, then the step
+      constexpr int V = kVarRho, P = kVarRho | kPress;
+      switch (mode) {
+        case P: launch_mode<S, R, DEV, P>(la, a, st); return;
+        case P | kCurv: launch_mode<S, R, DEV, P | kCurv>(la, a, st); return;
+        case V | kStore: launch_mode<S, R, DEV, V | kStore>(la, a, st); return;
+        case V | kStore | kDiag: launch_mode<S, R, DEV, V | kStore | kDiag>(la, a, st); return;
+        case V | kFields: launch_mode<S, R, DEV, V | kFields>(la, a, st); return;
+        case V | kDiag: launch_mode<S, R, DEV, V | kDiag>(la, a, st); return;
+        case V | kStore | kCurv: launch_mode<S, R, DEV, V | kStore | kCurv>(la, a, st); return;
+        case V | kStore | kDiag | kCurv:
+          launch_mode<S, R, DEV, V | kStore | kDiag | kCurv>(la, a, st); return;
+        case V | kFields | kCurv: launch_mode<S, R, DEV, V | kFields | kCurv>(la, a, st); return;
+        case V | kDiag | kCurv: launch_mode<S, R, DEV, V | kDiag | kCurv>(la, a, st); return;
+        default: break;
       }
       launch_mode<S, R, DEV, kFields | kDiag>(la, a, st);
       break;
+    }
   }
 }
 
@@ -332,7 +329,11 @@ int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
   if (a.drho != 0.0) {
     // two densities: the pressure of Eq. 9 of the source state first (it
     // needs u, hence the force, at every site of the stencil)
-    launch_prec<double, double, false>(kVarRho | kPress | (mode & kCurv), h->la, a, h->stream);
+    const int pm = kVarRho | kPress | (mode & kCurv);
+    if (h->P.precision == LBE_CSF_FP64)
+      launch_prec<double, double, false>(pm, h->la, a, h->stream);
+    else
+      launch_prec<float, float, true>(pm, h->la, a, h->stream);
     HIPCHK(h, hipGetLastError());
     mode |= kVarRho;
   }
@@ -557,8 +558,8 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   else
     init_kernel<float, true><<<grid, 256, 0, h->stream>>>(
         static_cast<float *>(h->state[0]), phi0, T0, nx, ny, params->walls_y, beta2, eps2,
-        gam3, h->base.rcv, params->p0, params->T_shift, params->T_grad, h->base.rho, 0.0,
-        h->base.cv);
+        gam3, h->base.rcv, params->p0, params->T_shift, params->T_grad, h->base.rho,
+        h->base.drho, h->base.cv);
   e = hipGetLastError();
   if (e != hipSuccess) {
     h->err = std::string("init kernel: ") + hipGetErrorString(e);

@@ -84,11 +84,15 @@ struct RowVals {
 };
 
 // Moments of a loaded site: c (FP64), T or Delta T (FP64), p or Delta p
-// (sum f).  With two densities T = sum hbar / (rho(c) cv).
+// (sum f).  With two densities T = sum hbar / (rho(c) cv); in the FP32 form
+// the stored hbar deviates from w rho cv Trow (rho of the c = 0 fluid), so
+// Delta T = (sum of deviations - c drho cv Trow) / (rho(c) cv), Trow given
+// as tref.
 template <typename R, bool VR = false>
 __device__ __forceinline__ void site_moments(const RowVals<R> &r, double inv_rcv, double *c,
                                              double *T, R *p, double rho = 0.0,
-                                             double drho = 0.0, double cv = 0.0) {
+                                             double drho = 0.0, double cv = 0.0,
+                                             double tref = 0.0) {
   R cs = 0, hs = 0, f = 0;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -100,7 +104,7 @@ __device__ __forceinline__ void site_moments(const RowVals<R> &r, double inv_rcv
   }
   *c = r.g0 + double(cs);
   if (VR)
-    *T = (r.h0 + double(hs)) / ((rho + *c * drho) * cv);
+    *T = (r.h0 + double(hs) - *c * drho * cv * tref) / ((rho + *c * drho) * cv);
   else
     *T = (r.h0 + double(hs)) * inv_rcv;
   *p = f;
@@ -246,7 +250,10 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
 #pragma unroll
     for (int q = 1; q < 9; ++q) hs += double(cur.v[18 + q]);
     const double rcv_s = VR ? rho_s * a.cv : a.rcv;
-    const double Td = (cur.h0 + hs) / rcv_s;          // T or Delta T, FP64
+    // two densities, FP32 form: the deviations are taken from w rho cv Trow
+    // with the density of the c = 0 fluid; hoff = (rho(c) - rho) cv Trow
+    const double hoff_d = (VR && DEV) ? cd * a.drho * a.cv * Trow : 0.0;
+    const double Td = (cur.h0 + hs - hoff_d) / rcv_s;   // T or Delta T, FP64
     const double Tfull_d = DEV ? Td + Trow : Td;
     const R Tfull = R(Tfull_d);
     const R rcvT = (VR ? R(rcv_s) : k.rcv) * Tfull;
@@ -312,7 +319,11 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       }
       const R geq = w * gmu + c * G;
       const R go = cur.v[9 + i] - wg * (cur.v[9 + i] - geq) + gsrc;
-      const R heq = DEV ? k.rcv * (Tv * w + Tfull * G) : heq_full;
+      R heq;
+      if constexpr (DEV && VR)
+        heq = R(rcv_s) * (Tv * w + Tfull * G) + w * R(hoff_d);
+      else
+        heq = DEV ? k.rcv * (Tv * w + Tfull * G) : heq_full;
       const R ho = cur.v[18 + i] - wT * (cur.v[18 + i] - heq) + hsrc;
       dg += cur.v[9 + i] - go;
       // push to x + xi_i
@@ -324,7 +335,10 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
         const R twv = DEV ? R(tw[x] - Trow) : R(tw[x]);
         st(o, s_own, fo);
         st(9 + o, s_own, go);
-        st(18 + o, s_own, R(2) * w * (VR ? R(rcv_s) : k.rcv) * twv - ho);
+        if constexpr (DEV && VR)
+          st(18 + o, s_own, R(2) * w * (R(rcv_s) * twv + R(hoff_d)) - ho);
+        else
+          st(18 + o, s_own, R(2) * w * (VR ? R(rcv_s) : k.rcv) * twv - ho);
         dh += cur.v[18 + i] - ho;
       } else {
         int xd = x + kEx[i];
@@ -472,15 +486,17 @@ step_kernel(const StepArgs a) {
       }
     }
   };
-  // with two densities (FP64 form) the ring's pressure is that of Eq. 9,
-  // computed by the pressure pass of the same source state
+  // with two densities the ring's pressure is that of Eq. 9, computed by the
+  // pressure pass of the same source state
   constexpr bool VR = (MODE & kVarRho) != 0;
   constexpr bool VRP = VR && !(MODE & kPress);
+  // the FP32 form's temperature reference at the centre of a row
+  auto tref_of = [&](int row) { return DEV ? a.Ts + a.Tg * (double(row) + 0.5) : 0.0; };
   auto put_own = [&](int slot, const RowVals<R> &r, int row) {
     if (act) {
       double c, T;
       R p;
-      site_moments<R, VR>(r, inv_rcv, &c, &T, &p, a.rho, a.drho, a.cv);
+      site_moments<R, VR>(r, inv_rcv, &c, &T, &p, a.rho, a.drho, a.cv, tref_of(row));
       ringc[slot][lane + 1] = c;
       ringt[slot][lane + 1] = R(T);
       ringp[slot][lane + 1] = VRP ? R(a.pc[(size_t)row * nx + x]) : p;
@@ -525,7 +541,8 @@ step_kernel(const StepArgs a) {
 #pragma unroll
           for (int q = 1; q < 9; ++q) cs += ld(9 + q, s);
           const double ch = ldd(0, s) + double(cs);
-          ringt[slot][hpos] = R((ldd(1, s) + double(hs)) / ((a.rho + ch * a.drho) * a.cv));
+          ringt[slot][hpos] = R((ldd(1, s) + double(hs) - ch * a.drho * a.cv * tref_of(row)) /
+                                ((a.rho + ch * a.drho) * a.cv));
         } else {
           ringt[slot][hpos] = R((ldd(1, s) + double(hs)) * inv_rcv);
         }
@@ -628,7 +645,7 @@ step_kernel(const StepArgs a) {
   }
   if (MODE & kDiag)
     block_partials<NW>(acc, red, lane, a.partials + (size_t)blockIdx.x * kNumPartials);
-  static_assert(!VR || (PIPE == 1 && !DEV), "two densities: FP64 form, rows one ahead");
+  static_assert(!VR || PIPE == 1, "two densities: rows loaded one ahead");
 }
 
 }  // namespace lbe

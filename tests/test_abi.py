@@ -110,9 +110,9 @@ def test_create_rejects_before_device_work(binding):
 
 def test_force_form_and_density_parameters(binding):
     """csf_form must be 0 or 1; rho2 >= 0 (0: one density); two densities
-    need the FP64 form and add one FP64 plane (the pressure of Eq. 9) to the
-    workspace; a grid whose state would pass 4 GiB is refused, and so is a
-    linear thermal reference (T_grad) in the FP32 form with periodic y."""
+    add one FP64 plane (the pressure of Eq. 9) to the workspace in either
+    form; a grid whose state would pass 4 GiB is refused, and so is a linear
+    thermal reference (T_grad) in the FP32 form with periodic y."""
     from paper_1412_6238_amd import workloads as wl
     p = wl.make("planar_marangoni")["params"]
     n = p["nx"] * p["ny"]
@@ -121,9 +121,12 @@ def test_force_form_and_density_parameters(binding):
     assert binding.workspace_bytes(binding.make_params(dict(p, rho2=p["rho"]), "fp64")) == base
     two = binding.workspace_bytes(binding.make_params(dict(p, rho2=2.0), "fp64"))
     assert two - base == (n * 8 + 255) // 256 * 256
+    base32 = binding.workspace_bytes(binding.make_params(p, "fp32_dev"))
+    two32 = binding.workspace_bytes(binding.make_params(dict(p, rho2=2.0), "fp32_dev"))
+    assert two32 - base32 == (n * 8 + 255) // 256 * 256
     for bad, prec in ((dict(csf_form=2), "fp64"), (dict(csf_form=-1), "fp32_dev"),
                       (dict(rho2=-1.0), "fp64"), (dict(rho2=float("inf")), "fp64"),
-                      (dict(rho2=2.0), "fp32_dev"), (dict(nx=8192, ny=8192), "fp32_dev"),
+                      (dict(nx=8192, ny=8192), "fp32_dev"),
                       (dict(walls_y=0, T_grad=0.01), "fp32_dev"),
                       (dict(nx=4096, ny=8192), "fp64")):
         with pytest.raises(binding.LbeCsfError) as e:

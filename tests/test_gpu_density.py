@@ -6,8 +6,9 @@ pass before every step) and F-bar of Sec. III.  The HIP path is held to the
 FP64 oracle at 1e-12 on random states, grids with walls and periodic y,
 ragged strips, both capillary forms and the 4096 x 4096 grid on sampled
 windows; strip shapes agree bitwise; the layered channel reaches its
-diffuse-interface steady state.  The FP32 form and the adjoint refuse two
-densities.
+diffuse-interface steady state.  The FP32 deviation form is held to the FP64
+path at 1e-4 relative L2 on phi, u and T over long runs.  The adjoint
+refuses two densities.
 """
 import os
 import sys
@@ -220,15 +221,104 @@ def test_two_densities_full_size_sampled(lbe, oracle_mod):
     _say(f"  compared {checked} sites in {len(wins)} windows")
 
 
-def test_two_densities_refused_where_unsupported(lbe):
+def test_two_densities_refuse_recording(lbe):
+    """The adjoint covers one density only: a recorded run is refused."""
     base = wl.random_case(16, 16, seed=3)
     case = _two(base, 2.0 * base["params"]["rho"])
-    with pytest.raises(lbe.LbeCsfError) as e:
-        lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
-                       case["Twall_top"], precision="fp32_dev")
-    assert e.value.status == lbe.LBE_CSF_EINVAL
-    sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
-                         case["Twall_top"], record_steps=8)
-    with pytest.raises(lbe.LbeCsfError) as e:
-        sim.step(4, record=True)
-    assert e.value.status == lbe.LBE_CSF_EINVAL
+    for prec in ("fp64", "fp32_dev"):
+        sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                             case["Twall_top"], precision=prec, record_steps=8)
+        with pytest.raises(lbe.LbeCsfError) as e:
+            sim.step(4, record=True)
+        assert e.value.status == lbe.LBE_CSF_EINVAL
+        sim.step(4)
+
+
+def _fp32_vs_fp64(lbe, w, nsteps, what, tol=1e-4):
+    """Run both forms from the same inputs; relative L2 of the FP32 form's
+    phi, u and T against the FP64 path."""
+    res = {}
+    for prec in ("fp64", "fp32_dev"):
+        sim = lbe.Simulation(w["params"], w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"],
+                             precision=prec)
+        sim.step(nsteps)
+        assert sim.diagnostics()["n_nonfinite"] == 0
+        res[prec] = _fields_np(sim)
+        del sim
+    a, b = res["fp32_dev"], res["fp64"]
+    e = {"phi": _rel(a["phi"], b["phi"]),
+         "u": _rel(np.stack([a["ux"], a["uy"]]), np.stack([b["ux"], b["uy"]])),
+         "T": _rel(a["T"], b["T"])}
+    _say(f"  {what}: fp32_dev vs fp64 " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    for k, v in e.items():
+        assert v <= tol, (what, k, v)
+    return a, b
+
+
+@pytest.mark.parametrize("nx,ny,walls,ratio", GRIDS)
+def test_two_densities_fp32_random(lbe, nx, ny, walls, ratio):
+    """The FP32 form on the random cases of the parity test (density ratios
+    0.25 to 5, walls and periodic y), 50 steps."""
+    base = wl.random_case(nx, ny, seed=5 * nx + ny, walls_y=walls)
+    case = _two(base, ratio * base["params"]["rho"], p0=0.0)
+    _say(f"case two densities fp32 random {nx}x{ny} walls={walls} ratio={ratio}")
+    _fp32_vs_fp64(lbe, case, 50, f"{nx}x{ny}")
+
+
+@pytest.mark.parametrize("name,nsteps,kw", [("e1", 100000, {}), ("e3", 40000, {}),
+                                            ("e3", 40000, {"csf_form": 1}),
+                                            ("e1", 100000, {"rho2": 5.0})])
+def test_two_densities_fp32_paper_geometries(lbe, name, nsteps, kw):
+    """The paper's layered channel and droplet with a density ratio of 2 (5
+    for one channel run), both force forms: the FP32 form against FP64 over
+    long runs."""
+    kw = dict({"rho2": 2.0}, **kw)
+    w = wl.paper_case(name, **kw)
+    _say(f"case two densities fp32 paper {name} {kw} {nsteps} steps")
+    _fp32_vs_fp64(lbe, w, nsteps, name)
+
+
+def test_two_densities_fp32_channel(lbe):
+    """The layered channel (rho 1 below, 3 above) to its steady state in the
+    FP32 form: within 1e-4 of the FP64 path and within the same bars of the
+    diffuse-interface balances as the FP64 run."""
+    nx, ny = 4, 64
+    p = wl.base_params(nx, ny, tau_f=(0.8, 0.8), tau_T=(0.8, 1.1), tau_g=2.5, mobility=0.1,
+                       width=4.0, sigma0=1e-3, sigmaT=0.0, force=(1e-6, 0.0), rho=1.0, rho2=3.0,
+                       T_shift=0.0, T_grad=1.0 / ny)
+    Y, _ = wl.coords(nx, ny)
+    w = dict(params=p, phi0=wl.tanh_layer(nx, ny, ny / 2, 4.0), T0=Y / ny,
+             Twall_bot=np.zeros(nx), Twall_top=np.ones(nx))
+    _say("case two densities fp32 channel 4x64 60000 steps")
+    a, _ = _fp32_vs_fp64(lbe, w, 60000, "channel")
+    u_d, T_d = an.layered_1d_steady(ny, ny / 2, 4.0, 0, 0, 0, 0, 1e-6, 0.0, 1.0, rho1=1.0,
+                                    rho2=3.0, tau=(p["tau_f"], p["tau_T"]))
+    eu, eT = _rel(a["ux"].mean(axis=1), u_d), _rel(a["T"].mean(axis=1), T_d)
+    _say(f"  u {eu:.2e} T {eT:.2e}")
+    assert eu <= 5e-3 and eT <= 4e-3
+
+
+def test_two_densities_fp32_multi_droplet(lbe):
+    """4096 x 4096 multi-droplet workload with droplets twice as dense as the
+    matrix, 2000 steps in each form."""
+    w = wl.make("multi_droplet", rho2=2.0)
+    _say("case two densities fp32 multi_droplet 4096x4096 2000 steps")
+    _fp32_vs_fp64(lbe, w, 2000, "multi_droplet")
+
+
+def test_two_densities_fp32_launch_shapes_agree(lbe, monkeypatch):
+    """FP32 form: strip widths and chunk heights give the same state, bit for
+    bit."""
+    base = wl.random_case(300, 40, seed=45, walls_y=1)
+    case = _two(base, 2.5 * base["params"]["rho"])
+    out = []
+    for nw, rows in (("4", "40"), ("1", "7"), ("2", "9"), ("8", "13")):
+        monkeypatch.setenv("LBE_CSF_NW", nw)
+        monkeypatch.setenv("LBE_CSF_ROWS", rows)
+        _say(f"case two densities fp32 launch nw={nw} rows={rows}")
+        sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                             case["Twall_top"], precision="fp32_dev")
+        sim.step(5)
+        out.append(sim.get_state().cpu().numpy())
+    for o in out[1:]:
+        np.testing.assert_array_equal(o, out[0])

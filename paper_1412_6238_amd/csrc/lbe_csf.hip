@@ -45,7 +45,9 @@ struct Launch {
   int nblocks;
 };
 
-Launch pick_launch(int nx, int ny, bool fp32) {
+// two_ahead: the step may load rows two ahead (not with two densities, whose
+// step loads one row ahead)
+Launch pick_launch(int nx, int ny, bool fp32, bool two_ahead) {
   Launch L;
   // Strip width: four waves on wide grids, two from 256 columns; a narrower
   // grid takes one strip across its whole width with at least two waves
@@ -68,7 +70,7 @@ Launch pick_launch(int nx, int ny, bool fp32) {
   };
   int rows = rows_for(2048);
   L.pipe = 1;
-  if (fp32 && rows >= 64 && nx >= 4096 && !std::getenv("LBE_CSF_NW")) {
+  if (fp32 && two_ahead && rows >= 64 && nx >= 4096 && !std::getenv("LBE_CSF_NW")) {
     // large grids: one block of eight waves (512 columns) per CU, marching
     // long chunks; the best shape measured on 4096^2 (20.6k MLUPS)
     L.nw = 8;
@@ -88,6 +90,10 @@ Launch pick_launch(int nx, int ny, bool fp32) {
     const int v = std::atoi(e);
     if (v == 0 || v == 1 || v == 2) L.pipe = v;
   }
+  // two densities load rows one ahead; without the eight-wave shape above
+  // the FP32 form gets 4-wave strips with 64-row chunks on 4096^2 (measured
+  // 11.9k MLUPS, against 10.7k on eight-wave strips)
+  if (!two_ahead) L.pipe = 1;
   if (const char *e = std::getenv("LBE_CSF_ROWS")) {
     const int v = std::atoi(e);
     if (v >= 1) rows = v;
@@ -151,7 +157,7 @@ Layout make_layout(const lbe_csf_params *p, int64_t record_steps) {
   const size_t n = (size_t)p->nx * p->ny;
   const size_t vb = p->precision == LBE_CSF_FP64 ? 8 : 4;
   L.state_bytes = kNumS * n * vb + 2 * n * 8;   // 25 planes + FP64 g_0, hbar_0
-  const Launch la = pick_launch(p->nx, p->ny, p->precision == LBE_CSF_FP32_DEV);
+  const Launch la = pick_launch(p->nx, p->ny, p->precision == LBE_CSF_FP32_DEV, !two_densities(p));
   size_t o = 0;
   L.off_a = o; o = align_up(o + L.state_bytes);
   L.off_b = o; o = align_up(o + L.state_bytes);
@@ -512,7 +518,8 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   if (!h) return fail(nullptr, LBE_CSF_ENOMEM, "host allocation failed");
   h->P = *params;
   h->L = L;
-  h->la = pick_launch(params->nx, params->ny, params->precision == LBE_CSF_FP32_DEV);
+  h->la = pick_launch(params->nx, params->ny, params->precision == LBE_CSF_FP32_DEV,
+                      !two_densities(params));
   h->stream = static_cast<hipStream_t>(stream);
   h->ws = static_cast<char *>(workspace);
   h->state[0] = h->ws + L.off_a;

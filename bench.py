@@ -141,6 +141,8 @@ def main():
                     help="capillary part of the CSF force: 0 potential form (default), "
                          "1 curvature form as printed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error-check", action="store_true",
+                    help="skip the FP64 run that states the FP32 form's error")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--adjoint", action="store_true",
                     help="time the differentiated droplet run instead: a recorded forward "
@@ -241,7 +243,27 @@ def main():
         "n_nonfinite": d_last["n_nonfinite"],
         "kernel_hash": kernel_hash(),
     }
-    del sim
+    if args.precision == "fp32_dev" and not args.no_error_check:
+        # the FP32 form's error at this step count: the FP64 path run from the
+        # same inputs for the same number of steps (outside the timed region)
+        a = sim.fields()
+        del sim
+        torch.cuda.empty_cache()
+        ref = lbe_csf.Simulation(p, w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"],
+                                 precision="fp64", diag_every=0)
+        ref.step(args.warmup + args.steps)
+        b = ref.fields()
+        del ref
+        rel = lambda x, y: float(torch.linalg.norm(x - y) / torch.linalg.norm(y))
+        out["fp32_vs_fp64"] = {
+            "steps": args.warmup + args.steps,
+            "phi": rel(a["phi"], b["phi"]),
+            "u": rel(torch.stack([a["ux"], a["uy"]]), torch.stack([b["ux"], b["uy"]])),
+            "T": rel(a["T"], b["T"]),
+            "measure": "relative L2 of the FP32 form's fields against the FP64 path"}
+        del a, b
+    else:
+        del sim
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

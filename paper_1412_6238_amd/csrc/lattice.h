@@ -28,7 +28,7 @@ enum : int {
   kDiag = 4,    // per-block FP64 partial sums of the diagnostics
   kTape = 8,    // write the moments of the source state to the tape
   kCurv = 16,   // capillary force in the curvature form of Eq. 4
-  kVarRho = 32, // two densities, rho(c) = rho + c drho (FP64 form)
+  kVarRho = 32, // two densities, rho(c) = rho + c drho
   kPress = 64   // with kVarRho: only the pressure of Eq. 9, into a plane
 };
 

@@ -29,7 +29,9 @@ enum : int {
   kTape = 8,    // write the moments of the source state to the tape
   kCurv = 16,   // capillary force in the curvature form of Eq. 4
   kVarRho = 32, // two densities, rho(c) = rho + c drho
-  kPress = 64   // with kVarRho: only the pressure of Eq. 9, into a plane
+  kPress = 64,  // with kVarRho: only the pressure of Eq. 9, into a plane
+  kStream = 128 // FP32 form, state larger than the last-level cache: stores
+                // that write whole lines bypass that cache (buf_store_stream)
 };
 
 constexpr int kNumPartials = 7;  // mass, energy, cy, cx, mass_thr, cuy_thr, nonfinite
@@ -106,6 +108,26 @@ __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_
     using V2 = __attribute__((ext_vector_type(2))) uint32_t;
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)byte_off,
                                           (int)base, 0);
+  }
+}
+
+// The same store marked non-temporal.  With kStream the FP32 step uses it for
+// the stores whose lines one wave writes whole (the rest populations and the
+// moves along y): the lines then go to HBM without displacing the lines that
+// the shifted stores of neighbouring waves are still merging.  Measured on
+// 4096^2: 1.3-1.7% faster; on a 512 x 1024 grid, whose two states fit in the
+// MI355X's 256 MB last-level cache, 5-9% slower, hence the size test on the
+// host.
+template <typename T>
+__device__ __forceinline__ void buf_store_stream(T v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off,
+                                                 uint32_t base = 0) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)byte_off,
+                                          (int)base, 2);
+  } else {
+    using V2 = __attribute__((ext_vector_type(2))) uint32_t;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)byte_off,
+                                          (int)base, 2);
   }
 }
 

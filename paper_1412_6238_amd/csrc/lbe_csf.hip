@@ -32,6 +32,7 @@ namespace {
 
 constexpr int kDiagRing = 4096;
 constexpr int kNumCUs = 256;   // compute units of an MI355X (gfx950)
+constexpr size_t kLastLevelCache = size_t(256) << 20;   // MI355X Infinity Cache
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -43,6 +44,7 @@ struct Launch {
   int rows;      // rows per chunk
   int nchunks;
   int nblocks;
+  bool stream;   // plain FP32 steps use kStream (state beyond the last-level cache)
 };
 
 // two_ahead: the step may load rows two ahead (not with two densities, whose
@@ -101,6 +103,7 @@ Launch pick_launch(int nx, int ny, bool fp32, bool two_ahead) {
   L.rows = std::min(rows, ny);
   L.nchunks = (ny + L.rows - 1) / L.rows;
   L.nblocks = L.nstrips * L.nchunks;
+  L.stream = false;
   return L;
 }
 
@@ -297,6 +300,23 @@ void launch_prec(int mode, const Launch &la, const StepArgs &a, hipStream_t st) 
     case kDiag | kCurv: launch_mode<S, R, DEV, kDiag | kCurv>(la, a, st); break;
     case kStore | kTape | kCurv: launch_mode<S, R, DEV, kStore | kTape | kCurv>(la, a, st); break;
     case kTape | kCurv: launch_mode<S, R, DEV, kTape | kCurv>(la, a, st); break;
+    case kStore | kStream:
+    case kStore | kDiag | kStream:
+    case kStore | kCurv | kStream:
+    case kStore | kDiag | kCurv | kStream:
+      if constexpr (DEV) {
+        constexpr int T = kStream;
+        switch (mode) {
+          case kStore | T: launch_mode<S, R, DEV, kStore | T>(la, a, st); return;
+          case kStore | kDiag | T: launch_mode<S, R, DEV, kStore | kDiag | T>(la, a, st); return;
+          case kStore | kCurv | T: launch_mode<S, R, DEV, kStore | kCurv | T>(la, a, st); return;
+          default:
+            launch_mode<S, R, DEV, kStore | kDiag | kCurv | T>(la, a, st); return;
+        }
+      } else {
+        launch_prec<S, R, DEV>(mode & ~kStream, la, a, st);   // FP32 form only
+      }
+      break;
     default: {
       // two densities: the pressure pass, then the step
       constexpr int V = kVarRho, P = kVarRho | kPress;
@@ -332,6 +352,7 @@ int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
   a.p = p;
   a.T = T;
   if (h->P.csf_form == 1) mode |= kCurv;
+  if (h->la.stream && (mode & kStore) && !(mode & kTape)) mode |= kStream;
   if (a.drho != 0.0) {
     // two densities: the pressure of Eq. 9 of the source state first (it
     // needs u, hence the force, at every site of the stencil)
@@ -520,6 +541,15 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   h->L = L;
   h->la = pick_launch(params->nx, params->ny, params->precision == LBE_CSF_FP32_DEV,
                       !two_densities(params));
+  // the FP32 one-density step streams whole-line stores past the last-level
+  // cache when one step's source and destination states do not fit in it
+  h->la.stream = params->precision == LBE_CSF_FP32_DEV && !two_densities(params) &&
+                 2 * L.state_bytes > kLastLevelCache;
+  if (const char *e = std::getenv("LBE_CSF_STREAM")) {
+    const int v = std::atoi(e);
+    if (v == 0 || v == 1)
+      h->la.stream = v == 1 && params->precision == LBE_CSF_FP32_DEV && !two_densities(params);
+  }
   h->stream = static_cast<hipStream_t>(stream);
   h->ws = static_cast<char *>(workspace);
   h->state[0] = h->ws + L.off_a;

@@ -40,7 +40,8 @@
 // diagnostic partials), kFields (macroscopic output), kTape (moments for the
 // adjoint), kCurv (capillary force in the curvature form of Eq. 4), kVarRho
 // (two densities; the ring then holds the pressure of Eq. 9, which a
-// kVarRho | kPress launch of the same kernel writes first).
+// kVarRho | kPress launch of the same kernel writes first), kStream (whole-line
+// stores bypass the last-level cache; FP32 form on large grids).
 //
 // Two arithmetic forms share the templates:
 //   R = double, DEV = false: FP64 values as defined by the paper;
@@ -271,6 +272,15 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     auto st = [&](int q, uint32_t off, R val) {
       buf_store<S>(S(val), rd, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes);
     };
+    // stores whose lines this wave writes whole
+    constexpr bool stream = (MODE & kStream) != 0;
+    auto st_whole = [&](int q, uint32_t off, R val) {
+      if constexpr (stream)
+        buf_store_stream<S>(S(val), rd, off * (uint32_t)sizeof(S),
+                            (uint32_t)plane_of(q) * pbytes);
+      else
+        buf_store<S>(S(val), rd, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes);
+    };
     // FP32 form: what the eight moving populations of g and hbar give away in
     // this collision, as stored (sum of old - new, each difference of two
     // nearby FP32 values)
@@ -310,7 +320,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const R heq_full = rcvT * gam;
       const R hsrc = chf * src_h * fhe * heq_full;
       if (i == 0) {
-        st(0, s_own, fo);
+        st_whole(0, s_own, fo);
         gsrc0 = gsrc;
         hsrc0 = hsrc;
         G0 = G;
@@ -346,12 +356,20 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
         int yd = j + kEy[i];
         yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
         const uint32_t s = (uint32_t)(yd * nx + xd);
-        st(i, s, fo);
-        st(9 + i, s, go);
+        if (kEx[i] == 0) {
+          st_whole(i, s, fo);
+          st_whole(9 + i, s, go);
+        } else {
+          st(i, s, fo);
+          st(9 + i, s, go);
+        }
         // a move to the next row changes the reference by Tg xi_y
         const R shift = DEV && kEy[i] != 0 ? R(kEy[i]) * w * k.rcv * R(a.Tg) : R(0);
         const R hst = ho - shift;
-        st(18 + i, s, hst);
+        if (kEx[i] == 0)
+          st_whole(18 + i, s, hst);
+        else
+          st(18 + i, s, hst);
         dh += (cur.v[18 + i] - hst) - shift;
       }
     }
@@ -372,8 +390,13 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const double hdiff = cur.h0 - rcv_s * Tfull_d * double(gam0);
       hnew = cur.h0 + double(-wT * R(hdiff) + hsrc0);
     }
-    buf_store<double>(gnew, rd, s_own * 8u, dbase);
-    buf_store<double>(hnew, rd, s_own * 8u, dbase + (uint32_t)(n * 8));
+    if constexpr (stream) {
+      buf_store_stream<double>(gnew, rd, s_own * 8u, dbase);
+      buf_store_stream<double>(hnew, rd, s_own * 8u, dbase + (uint32_t)(n * 8));
+    } else {
+      buf_store<double>(gnew, rd, s_own * 8u, dbase);
+      buf_store<double>(hnew, rd, s_own * 8u, dbase + (uint32_t)(n * 8));
+    }
   }
 }
 

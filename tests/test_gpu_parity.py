@@ -197,6 +197,24 @@ def test_row_pipelines_agree(lbe, oracle_mod, monkeypatch, pipe, precision):
         _cmp({"F": F}, {"F": orc.state()}, what="F")
 
 
+@pytest.mark.parametrize("extra", [{}, {"csf_form": 1}, {"rho2": 2.0}])
+def test_fp32_store_policy_does_not_matter(lbe, monkeypatch, extra):
+    """The FP32 form's whole-line stores with and without the cache bypass
+    (chosen by state size; forced both ways here) give the same state, bit
+    for bit."""
+    case = wl.random_case(136, 40, seed=31, walls_y=1)
+    p = dict(case["params"], **extra)
+    out = []
+    for policy in ("0", "1"):
+        monkeypatch.setenv("LBE_CSF_STREAM", policy)
+        _say(f"case fp32 store policy {policy} {extra}")
+        sim = lbe.Simulation(p, case["phi0"], case["T0"], case["Twall_bot"], case["Twall_top"],
+                             precision="fp32_dev")
+        sim.step(6)
+        out.append(sim.get_state().cpu().numpy())
+    np.testing.assert_array_equal(out[0], out[1])
+
+
 def test_fp64_chunking_does_not_matter(lbe, oracle_mod, monkeypatch):
     """Different strip widths and chunk heights give bitwise-identical states."""
     case = wl.random_case(200, 60, seed=12, walls_y=1)

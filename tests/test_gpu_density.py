@@ -234,21 +234,26 @@ def test_two_densities_refuse_recording(lbe):
         sim.step(4)
 
 
-def _fp32_vs_fp64(lbe, w, nsteps, what, tol=1e-4):
+def _fp32_vs_fp64(lbe, w, nsteps, what, tol=1e-4, state=False):
     """Run both forms from the same inputs; relative L2 of the FP32 form's
-    phi, u and T against the FP64 path."""
-    res = {}
+    phi, u and T against the FP64 path (and of the 27 distributions as
+    get_state returns them, with state=True)."""
+    res, F = {}, {}
     for prec in ("fp64", "fp32_dev"):
         sim = lbe.Simulation(w["params"], w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"],
                              precision=prec)
         sim.step(nsteps)
         assert sim.diagnostics()["n_nonfinite"] == 0
         res[prec] = _fields_np(sim)
+        if state:
+            F[prec] = sim.get_state().cpu().numpy()
         del sim
     a, b = res["fp32_dev"], res["fp64"]
     e = {"phi": _rel(a["phi"], b["phi"]),
          "u": _rel(np.stack([a["ux"], a["uy"]]), np.stack([b["ux"], b["uy"]])),
          "T": _rel(a["T"], b["T"])}
+    if state:
+        e["F"] = _rel(F["fp32_dev"], F["fp64"])
     _say(f"  {what}: fp32_dev vs fp64 " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
     for k, v in e.items():
         assert v <= tol, (what, k, v)
@@ -258,11 +263,12 @@ def _fp32_vs_fp64(lbe, w, nsteps, what, tol=1e-4):
 @pytest.mark.parametrize("nx,ny,walls,ratio", GRIDS)
 def test_two_densities_fp32_random(lbe, nx, ny, walls, ratio):
     """The FP32 form on the random cases of the parity test (density ratios
-    0.25 to 5, walls and periodic y), 50 steps."""
+    0.25 to 5, walls and periodic y), 50 steps; fields and the distributions
+    read back through get_state."""
     base = wl.random_case(nx, ny, seed=5 * nx + ny, walls_y=walls)
     case = _two(base, ratio * base["params"]["rho"], p0=0.0)
     _say(f"case two densities fp32 random {nx}x{ny} walls={walls} ratio={ratio}")
-    _fp32_vs_fp64(lbe, case, 50, f"{nx}x{ny}")
+    _fp32_vs_fp64(lbe, case, 50, f"{nx}x{ny}", state=True)
 
 
 @pytest.mark.parametrize("name,nsteps,kw", [("e1", 100000, {}), ("e3", 40000, {}),

@@ -67,8 +67,8 @@ typedef enum {
   LBE_CSF_FP64 = 0,     /* distributions stored and evolved in FP64            */
   LBE_CSF_FP32_DEV = 1  /* FP32 deviations from the rest-weight equilibrium:
                            f - w p0, g, hbar - w rho cv T_ref(y) with the
-                           linear reference T_ref = T_shift + T_grad y (FP64
-                           g_0, hbar_0 and FP64 sums for the diagnostics)    */
+                           linear reference T_ref = T_shift + T_grad y (g_0
+                           in FP64; FP64 sums for the diagnostics)          */
 } lbe_csf_precision;
 
 /* Parameters (plain data; lattice units, dt = dx = 1, cs^2 = 1/3). */

@@ -201,8 +201,8 @@ __device__ __forceinline__ void site_adjoint(const StepArgs &a, const Consts<R> 
     if (VARTAU) {
       R hd;   // h - heq
       if (i == 0) {
-        hd = R(DEV ? cur.h0 - a.rcv * (Td * double(w) + Tfull_d * double(G))
-                   : cur.h0 - a.rcv * Tfull_d * double(gam));
+        hd = R(DEV ? cur.h0() - a.rcv * (Td * double(w) + Tfull_d * double(G))
+                   : cur.h0() - a.rcv * Tfull_d * double(gam));
       } else {
         const R heq = DEV ? k.rcv * (Tv * w + Tfull * G) : rcvT * gam;
         hd = cur.v[18 + i] - heq;
@@ -423,13 +423,13 @@ adj_collide_kernel(const AdjArgs aa) {
     RowVals<R> cur;
     if (VARTAU) {
       const __amdgpu_buffer_rsrc_t rs =
-          plane_rsrc(a.src, kNumS * n * sizeof(R) + 2 * n * 8);
+          plane_rsrc(a.src, state_bytes_for<R>(n));
 #pragma unroll
       for (int q = 0; q < 27; ++q)
         if (q != 9 && q != 18)
           cur.v[q] = buf_load<R>(rs, s * (uint32_t)sizeof(R), (uint32_t)plane_of(q) * pb);
-      cur.g0 = buf_load<double>(rs, s * 8u, kNumS * pb);
-      cur.h0 = buf_load<double>(rs, s * 8u, kNumS * pb + (uint32_t)(n * 8));
+      cur.g0r = rest_load_raw<R, 0>(rs, s, (uint32_t)rest_base<R>(0, n));
+      cur.h0r = rest_load_raw<R, 1>(rs, s, (uint32_t)rest_base<R>(1, n));
     }
     constexpr int NA = CURV ? kAdjA : 7;
     R db[27], da[kAdjA];

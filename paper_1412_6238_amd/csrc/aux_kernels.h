@@ -11,7 +11,7 @@ namespace lbe {
 // equilibrium (Sec. II Eqs. 7, 13-14; Sec. III Eq. 22).  FP32 form: stored as
 // deviations, so f - w p0 = 0 and hbar - w rho cv Tr = w rho cv (T0 - Tr)
 // with the linear reference Tr = Ts + Tg (y + 1/2) of the site's row.
-// Layout as in step_kernel.h: 25 planes of S, then FP64 g_0 and hbar_0.
+// Layout as in step_kernel.h: 25 planes of S, then the rest planes g_0 and hbar_0.
 template <typename S, bool DEV>
 __global__ void __launch_bounds__(256)
 init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
@@ -23,7 +23,6 @@ init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
   if (x >= nx || y >= ny) return;
   const size_t n = (size_t)nx * ny;
   const size_t s = (size_t)y * nx + x;
-  double *Fd = reinterpret_cast<double *>(F + kNumS * n);
   auto cval = [&](int dx, int dy) {
     int xx = x + dx;
     xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
@@ -54,8 +53,8 @@ init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
     const double hv = DEV ? (drho != 0.0 ? w * (rcv_s * T - rcv * Tr) : w * rcv * (T - Tr))
                           : w * rcv_s * T;
     if (i == 0) {
-      Fd[s] = c - (1.0 - w) * gmu;
-      Fd[n + s] = hv;
+      rest_set<S, 0>(F, n, s, c - (1.0 - w) * gmu);
+      rest_set<S, 1>(F, n, s, hv);
     } else {
       F[plane_of(9 + i) * n + s] = S(w * gmu);
       F[plane_of(18 + i) * n + s] = S(hv);
@@ -108,7 +107,7 @@ diag_reduce_kernel(const double *__restrict__ partials, int nblocks,
   }
 }
 
-// FP64 [27][n] <-> storage form (25 planes of S + FP64 g_0, hbar_0).
+// FP64 [27][n] <-> storage form (25 planes of S + the rest planes g_0, hbar_0).
 template <typename S, bool DEV>
 __global__ void __launch_bounds__(256)
 state_to_f64(const S *__restrict__ F, double *__restrict__ out, int nx, int ny,
@@ -118,8 +117,8 @@ state_to_f64(const S *__restrict__ F, double *__restrict__ out, int nx, int ny,
   const int q = blockIdx.y;
   if (s >= n) return;
   const int i = q % 9;
-  const double *Fd = reinterpret_cast<const double *>(F + kNumS * n);
-  double v = q == 9 ? Fd[s] : (q == 18 ? Fd[n + s] : double(F[plane_of(q) * n + s]));
+  double v = q == 9 ? rest_get<S, 0>(F, n, s)
+                    : (q == 18 ? rest_get<S, 1>(F, n, s) : double(F[plane_of(q) * n + s]));
   if (DEV) {
     if (q < 9) v += wq<double>(i) * p0;
     else if (q >= 18) v += wq<double>(i) * rcv * (Ts + Tg * (double(s / nx) + 0.5));
@@ -141,9 +140,8 @@ state_from_f64(S *__restrict__ F, const double *__restrict__ in, int nx, int ny,
     if (q < 9) v -= wq<double>(i) * p0;
     else if (q >= 18) v -= wq<double>(i) * rcv * (Ts + Tg * (double(s / nx) + 0.5));
   }
-  double *Fd = reinterpret_cast<double *>(F + kNumS * n);
-  if (q == 9) Fd[s] = v;
-  else if (q == 18) Fd[n + s] = v;
+  if (q == 9) rest_set<S, 0>(F, n, s, v);
+  else if (q == 18) rest_set<S, 1>(F, n, s, v);
   else F[plane_of(q) * n + s] = S(v);
 }
 

@@ -3,7 +3,8 @@
 //
 // The library owns no device memory: every buffer is carved out of the
 // caller's workspace.  Layout (each region 256-byte aligned):
-//   state A, state B     25 planes (FP64, or FP32 deviations) + FP64 g_0, hbar_0
+//   state A, state B     25 planes (FP64, or FP32 deviations) + g_0 (FP64) and
+//                        hbar_0 (FP64, or an FP32 deviation)
 //   wall temperatures    2 * nx FP64 (bottom, top)
 //   partials             max blocks * 7 FP64 (per-block diagnostic sums)
 //   diag ring            4096 records of (step, 7 sums)
@@ -125,8 +126,9 @@ bool params_valid(const lbe_csf_params *p, std::string *why) {
   if (p->nx < 3 || p->ny < 3) return bad("nx and ny must be >= 3");
   // the kernels address a state through one buffer descriptor (32-bit byte
   // offsets): 25 planes of the storage type plus two FP64 planes < 4 GiB
-  const double vb = p->precision == LBE_CSF_FP64 ? 8.0 : 4.0;
-  if ((double)p->nx * (double)p->ny * (25.0 * vb + 16.0) >= 4294967296.0)
+  const double sb = p->precision == LBE_CSF_FP64 ? (double)state_bytes_for<double>(1)
+                                                 : (double)state_bytes_for<float>(1);
+  if ((double)p->nx * (double)p->ny * sb >= 4294967296.0)
     return bad("grid too large: a state must stay below 4 GiB");
   if (p->walls_y != 0 && p->walls_y != 1) return bad("walls_y must be 0 or 1");
   if (p->precision != LBE_CSF_FP64 && p->precision != LBE_CSF_FP32_DEV)
@@ -159,7 +161,7 @@ Layout make_layout(const lbe_csf_params *p, int64_t record_steps) {
   Layout L{};
   const size_t n = (size_t)p->nx * p->ny;
   const size_t vb = p->precision == LBE_CSF_FP64 ? 8 : 4;
-  L.state_bytes = kNumS * n * vb + 2 * n * 8;   // 25 planes + FP64 g_0, hbar_0
+  L.state_bytes = vb == 8 ? state_bytes_for<double>(n) : state_bytes_for<float>(n);
   const Launch la = pick_launch(p->nx, p->ny, p->precision == LBE_CSF_FP32_DEV, !two_densities(p));
   size_t o = 0;
   L.off_a = o; o = align_up(o + L.state_bytes);

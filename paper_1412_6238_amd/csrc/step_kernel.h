@@ -14,12 +14,13 @@
 //                and anti-bounce-back with the wall temperature for hbar
 //
 // State layout (structure of arrays, x fastest): 25 planes of the storage
-// type S -- f_0..8, g_1..8, hbar_1..8 -- then two FP64 planes, g_0 and
+// type S -- f_0..8, g_1..8, hbar_1..8 -- then the rest populations g_0 and
 // hbar_0.  The rest populations carry the two transported scalars (c = g_0 +
-// small terms, rho cv T = hbar_0 + eight smaller terms); keeping them in FP64
-// keeps c and T accurate to far below FP32 rounding, which matters because c
-// enters the force through eps^2 lap c and T through grad sigma.  The FP32
-// form therefore moves 2 x (25 x 4 + 2 x 8) = 232 bytes per site update.
+// small terms, rho cv T = hbar_0 + eight smaller terms).  g_0 stays FP64 in
+// both forms, which keeps c accurate to far below FP32 rounding (c enters
+// the force through eps^2 lap c); the FP32 form holds hbar_0 as an FP32
+// deviation.  The FP32 form therefore moves 2 x (26 x 4 + 8) = 224 bytes per
+// site update, against the 216 of 27 FP32 values.
 //
 // The state held is F_n (pre-collision).  A lane reads the planes of its own
 // site (coalesced, aligned) and pushes post-collision values to the
@@ -46,7 +47,7 @@
 // Two arithmetic forms share the templates:
 //   R = double, DEV = false: FP64 values as defined by the paper;
 //   R = float,  DEV = true : FP32 deviations f - w p0, g_{1..8},
-//     hbar_{1..8} - w rho cv Tr (and FP64 g_0, hbar_0 - w0 rho cv Tr), with
+//     hbar_{0..8} - w rho cv Tr (and FP64 g_0), with
 //     the linear reference Tr = Ts + Tg y taken at the row of the stored
 //     value (a population moving to the next row changes reference by
 //     w rho cv Tg xi_y);
@@ -59,10 +60,80 @@
 
 namespace lbe {
 
-constexpr int kNumS = 25;  // planes in the storage type; two FP64 planes follow
+constexpr int kNumS = 25;  // planes in the storage type; the two rest planes follow
 
-// plane of distribution q (0..26 = f, g, hbar; not 9 or 18, the FP64 planes)
+// plane of distribution q (0..26 = f, g, hbar; not 9 or 18, the rest planes)
 __host__ __device__ constexpr int plane_of(int q) { return q < 9 ? q : (q < 18 ? q - 1 : q - 2); }
+
+// Storage of the two rest populations (g_0, then hbar_0) after the 25 planes.
+// The FP64 form keeps both in FP64.  The FP32 form keeps g_0 in FP64 and
+// hbar_0 in FP32: c sits almost entirely in g_0, and its rounding enters the
+// force through eps^2 lap c (stored in FP32, or as 30-bit fixed point, g_0
+// gave the planar Marangoni velocity errors of 14% and 0.4% against the FP64
+// path), while hbar_0 is stored as the deviation from w_0 rho cv Tr(y), which
+// FP32 holds to far below the thermal signal (largest error 6e-6 in T over
+// the test cases).
+enum : int { kRestF64 = 0, kRestF32 = 1 };
+template <typename S>
+__host__ __device__ constexpr int rest_fmt(int which) {
+  return sizeof(S) == 8 || which == 0 ? kRestF64 : kRestF32;
+}
+template <typename S>
+__host__ __device__ constexpr uint32_t rest_bytes(int which) {
+  return rest_fmt<S>(which) == kRestF64 ? 8u : 4u;
+}
+// bytes of one state of n sites, and the byte offset of rest plane `which`
+template <typename S>
+__host__ __device__ constexpr size_t state_bytes_for(size_t n) {
+  return kNumS * n * sizeof(S) + n * (rest_bytes<S>(0) + rest_bytes<S>(1));
+}
+template <typename S>
+__host__ __device__ constexpr size_t rest_base(int which, size_t n) {
+  return kNumS * n * sizeof(S) + (which ? n * rest_bytes<S>(0) : 0);
+}
+
+// A rest population as stored (raw), and its value.  Rows loaded ahead keep
+// the raw word in registers: converting at the load would make the wave wait
+// for the load there, long before the row is used (measured: 20% slower).
+template <int F> struct RestRaw { using T = double; };
+template <> struct RestRaw<kRestF32> { using T = float; };
+template <int F>
+__device__ __forceinline__ double rest_decode(typename RestRaw<F>::T v) {
+  return double(v);
+}
+
+// rest population of a site through the state's buffer descriptor (base: the
+// plane's byte offset)
+template <typename S, int W>
+__device__ __forceinline__ typename RestRaw<rest_fmt<S>(W)>::T rest_load_raw(
+    __amdgpu_buffer_rsrc_t r, uint32_t site, uint32_t base) {
+  using T = typename RestRaw<rest_fmt<S>(W)>::T;
+  return buf_load<T>(r, site * (uint32_t)sizeof(T), base);
+}
+template <typename S, int W>
+__device__ __forceinline__ double rest_load(__amdgpu_buffer_rsrc_t r, uint32_t site,
+                                            uint32_t base) {
+  return rest_decode<rest_fmt<S>(W)>(rest_load_raw<S, W>(r, site, base));
+}
+template <typename S, int W, bool STREAM>
+__device__ __forceinline__ void rest_store(double v, __amdgpu_buffer_rsrc_t r, uint32_t site,
+                                           uint32_t base) {
+  using T = typename RestRaw<rest_fmt<S>(W)>::T;
+  if constexpr (STREAM) buf_store_stream<T>(T(v), r, site * (uint32_t)sizeof(T), base);
+  else buf_store<T>(T(v), r, site * (uint32_t)sizeof(T), base);
+}
+// the same through plain pointers (set-up and conversion kernels)
+template <typename S, int W>
+__device__ __forceinline__ double rest_get(const void *state, size_t n, size_t s) {
+  using T = typename RestRaw<rest_fmt<S>(W)>::T;
+  return double(reinterpret_cast<const T *>(static_cast<const char *>(state) +
+                                            rest_base<S>(W, n))[s]);
+}
+template <typename S, int W>
+__device__ __forceinline__ void rest_set(void *state, size_t n, size_t s, double v) {
+  using T = typename RestRaw<rest_fmt<S>(W)>::T;
+  reinterpret_cast<T *>(static_cast<char *>(state) + rest_base<S>(W, n))[s] = T(v);
+}
 
 // constants in the kernel's arithmetic type
 template <typename R>
@@ -77,11 +148,14 @@ struct Consts {
 };
 
 // One row of a lane's column: v[q] for the 25 storage planes (v[9], v[18]
-// unused) and the two FP64 rest populations.
+// unused) and the two rest populations as stored.
 template <typename R>
 struct RowVals {
   R v[27];
-  double g0, h0;
+  typename RestRaw<rest_fmt<R>(0)>::T g0r;
+  typename RestRaw<rest_fmt<R>(1)>::T h0r;
+  __device__ __forceinline__ double g0() const { return rest_decode<rest_fmt<R>(0)>(g0r); }
+  __device__ __forceinline__ double h0() const { return rest_decode<rest_fmt<R>(1)>(h0r); }
 };
 
 // Moments of a loaded site: c (FP64), T or Delta T (FP64), p or Delta p
@@ -103,11 +177,11 @@ __device__ __forceinline__ void site_moments(const RowVals<R> &r, double inv_rcv
       hs += r.v[18 + q];
     }
   }
-  *c = r.g0 + double(cs);
+  *c = r.g0() + double(cs);
   if (VR)
-    *T = (r.h0 + double(hs) - *c * drho * cv * tref) / ((rho + *c * drho) * cv);
+    *T = (r.h0() + double(hs) - *c * drho * cv * tref) / ((rho + *c * drho) * cv);
   else
-    *T = (r.h0 + double(hs)) * inv_rcv;
+    *T = (r.h0() + double(hs)) * inv_rcv;
   *p = f;
 }
 
@@ -237,9 +311,8 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
   if (MODE & kStore) {
     // one descriptor for the whole destination state (below 4 GiB); planes
     // are selected by a scalar offset
-    const __amdgpu_buffer_rsrc_t rd = plane_rsrc(a.dst, kNumS * n * sizeof(S) + 2 * n * 8);
+    const __amdgpu_buffer_rsrc_t rd = plane_rsrc(a.dst, state_bytes_for<S>(n));
     const uint32_t pbytes = (uint32_t)(n * sizeof(S));
-    const uint32_t dbase = kNumS * pbytes;
     const R ch = c < R(0) ? R(0) : (c > R(1) ? R(1) : c);
     const double wfd = 1.0 / (a.tauf0 + double(ch) * a.dtauf), cfd = 1.0 - 0.5 * wfd;
     const double usqd = uxd * uxd + uyd * uyd;
@@ -254,7 +327,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     // two densities, FP32 form: the deviations are taken from w rho cv Trow
     // with the density of the c = 0 fluid; hoff = (rho(c) - rho) cv Trow
     const double hoff_d = (VR && DEV) ? cd * a.drho * a.cv * Trow : 0.0;
-    const double Td = (cur.h0 + hs - hoff_d) / rcv_s;   // T or Delta T, FP64
+    const double Td = (cur.h0() + hs - hoff_d) / rcv_s;   // T or Delta T, FP64
     const double Tfull_d = DEV ? Td + Trow : Td;
     const R Tfull = R(Tfull_d);
     const R rcvT = (VR ? R(rcv_s) : k.rcv) * Tfull;
@@ -373,30 +446,26 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
         dh += (cur.v[18 + i] - hst) - shift;
       }
     }
-    // rest populations in FP64
+    // rest populations, formed in FP64
     double gnew, hnew;
     if (DEV) {
       // The collision conserves c = sum g and rho cv T = sum hbar at the site,
-      // so the FP64 rest populations receive exactly what the eight stored
-      // FP32 values gave away: the rounding of the stored values is taken up
-      // here, and c and T are transported without a systematic drift.
-      gnew = cur.g0 + double(dg);
-      hnew = cur.h0 + double(dh);
+      // so the rest populations receive exactly what the eight stored FP32
+      // values gave away: the FP64 g_0 takes up their rounding, and c is
+      // transported without a systematic drift; hbar_0 is then rounded once
+      // to its FP32 deviation.
+      gnew = cur.g0() + double(dg);
+      hnew = cur.h0() + double(dh);
     } else {
       // g^eq_0 - g_0 = sum_{q>0} g_q - (1 - w0) 3 Gamma mu + c G_0
       const R w0 = wq<R>(0);
       const R d0 = gsum - (R(1) - w0) * gmu + c * G0;
-      gnew = cur.g0 + double(wg * d0 + gsrc0);
-      const double hdiff = cur.h0 - rcv_s * Tfull_d * double(gam0);
-      hnew = cur.h0 + double(-wT * R(hdiff) + hsrc0);
+      gnew = cur.g0() + double(wg * d0 + gsrc0);
+      const double hdiff = cur.h0() - rcv_s * Tfull_d * double(gam0);
+      hnew = cur.h0() + double(-wT * R(hdiff) + hsrc0);
     }
-    if constexpr (stream) {
-      buf_store_stream<double>(gnew, rd, s_own * 8u, dbase);
-      buf_store_stream<double>(hnew, rd, s_own * 8u, dbase + (uint32_t)(n * 8));
-    } else {
-      buf_store<double>(gnew, rd, s_own * 8u, dbase);
-      buf_store<double>(hnew, rd, s_own * 8u, dbase + (uint32_t)(n * 8));
-    }
+    rest_store<S, 0, stream>(gnew, rd, s_own, (uint32_t)rest_base<S>(0, n));
+    rest_store<S, 1, stream>(hnew, rd, s_own, (uint32_t)rest_base<S>(1, n));
   }
 }
 
@@ -469,13 +538,14 @@ step_kernel(const StepArgs a) {
 
   // one descriptor for the whole source state (below 4 GiB); planes are
   // selected by a scalar offset
-  const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(src, kNumS * n * sizeof(S) + 2 * n * 8);
+  const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(src, state_bytes_for<S>(n));
   const uint32_t pbytes = (uint32_t)(n * sizeof(S));
   auto ld = [&](int q, uint32_t off) {
     return R(buf_load<S>(rsrc, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes));
   };
+  const uint32_t rb0 = (uint32_t)rest_base<S>(0, n), rb1 = (uint32_t)rest_base<S>(1, n);
   auto ldd = [&](int which, uint32_t off) {
-    return buf_load<double>(rsrc, off * 8u, kNumS * pbytes + (uint32_t)which * (uint32_t)(n * 8));
+    return which == 0 ? rest_load<S, 0>(rsrc, off, rb0) : rest_load<S, 1>(rsrc, off, rb1);
   };
   auto wrap_row = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
   auto is_ghost = [&](int row) { return walls && (row < 0 || row >= ny); };
@@ -486,15 +556,16 @@ step_kernel(const StepArgs a) {
 #pragma unroll
       for (int q = 0; q < 27; ++q)
         if (q != 9 && q != 18) r.v[q] = ld(q, s);
-      r.g0 = ldd(0, s);
-      r.h0 = ldd(1, s);
+      r.g0r = rest_load_raw<S, 0>(rsrc, s, rb0);
+      r.h0r = rest_load_raw<S, 1>(rsrc, s, rb1);
     }
   };
   // a helper lane's halo values: the nine planes of its field, and the FP64
   // rest population for c and T
   struct HaloVals {
     R v[9];
-    double d;
+    typename RestRaw<rest_fmt<S>(0)>::T g0r;   // c helpers
+    typename RestRaw<rest_fmt<S>(1)>::T h0r;   // T helpers
   };
   auto load_halo = [&](int row, HaloVals &h) {
     if (halo) {
@@ -505,7 +576,8 @@ step_kernel(const StepArgs a) {
       } else {
 #pragma unroll
         for (int q = 1; q < 9; ++q) h.v[q] = ld(9 * (hfield + 1) + q, s);
-        h.d = ldd(hfield, s);
+        if (hfield == 0) h.g0r = rest_load_raw<S, 0>(rsrc, s, rb0);
+        else h.h0r = rest_load_raw<S, 1>(rsrc, s, rb1);
       }
     }
   };
@@ -532,12 +604,12 @@ step_kernel(const StepArgs a) {
         R cs = 0;
 #pragma unroll
         for (int q = 1; q < 9; ++q) cs += h.v[q];
-        ringc[slot][hpos] = h.d + double(cs);
+        ringc[slot][hpos] = rest_decode<rest_fmt<S>(0)>(h.g0r) + double(cs);
       } else if (hfield == 1) {
         R hs = 0;
 #pragma unroll
         for (int q = 1; q < 9; ++q) hs += h.v[q];
-        ringt[slot][hpos] = R((h.d + double(hs)) * inv_rcv);
+        ringt[slot][hpos] = R((rest_decode<rest_fmt<S>(1)>(h.h0r) + double(hs)) * inv_rcv);
       } else {
         R f = 0;
 #pragma unroll
@@ -621,7 +693,8 @@ step_kernel(const StepArgs a) {
   HaloVals hnxt, hnxt2;
 #pragma unroll
   for (int q = 0; q < 27; ++q) cur.v[q] = nxt.v[q] = R(0);
-  cur.g0 = cur.h0 = nxt.g0 = nxt.h0 = 0.0;
+  cur.g0r = nxt.g0r = 0;
+  cur.h0r = nxt.h0r = 0;
   load_row(y0, cur);
   put_own(y0 & 3, cur, y0);
   put_halo_direct(y0 & 3, y0);

@@ -25,9 +25,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 # algorithmic bytes per site update: the 27 distributions read once and
-# written once; the FP32 form keeps 25 in FP32 and the two rest populations
-# (g_0, hbar_0) in FP64: 2 x (25 x 4 + 2 x 8) = 232; FP64: 2 x 27 x 8 = 432
-BYTES_PER_SITE = {"fp32_dev": 232, "fp64": 432}
+# written once, 4 bytes each in the FP32 form (216) and 8 in FP64 (432)
+BYTES_PER_SITE = {"fp32_dev": 216, "fp64": 432}
+# bytes the state layout actually moves per site update: the FP32 form keeps
+# the rest population g_0 in FP64, 2 x (26 x 4 + 8) = 224
+STORED_BYTES_PER_SITE = {"fp32_dev": 224, "fp64": 432}
+REPEATS = 5
 # the step kernel and its launch shape (chosen in lbe_csf.hip)
 KERNEL_SOURCES = ("paper_1412_6238_amd/csrc/step_kernel.h", "paper_1412_6238_amd/csrc/lattice.h",
                   "paper_1412_6238_amd/csrc/lbe_csf.hip")
@@ -53,31 +56,76 @@ def traffic_from_profile(workload, precision, sites, csf_form=0):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(w, seconds=15.0):
-    """The FP64 oracle on the host cores, on a band of the same workload
-    (the lowest 512 rows, full width, with the bottom wall), timed for about
-    `seconds`; MLUPS over the band's sites."""
-    import numpy as np
+def _oracle_band_mlups(w, rows, seconds, threads=None):
+    """MLUPS of the FP64 oracle stepping the lowest `rows` rows (full width,
+    with the bottom wall) of workload w for about `seconds`."""
     from oracle import oracle
     p = w["params"]
     nx = p["nx"]
-    rows = min(512, p["ny"])
-    win = (0, 0, nx, rows)
-    o = oracle.Oracle(p, w["Twall_bot"], w["Twall_top"], window=win)
+    rows = min(rows, p["ny"])
+    o = oracle.Oracle(p, w["Twall_bot"], w["Twall_top"], window=(0, 0, nx, rows))
     o.init(np.ascontiguousarray(w["phi0"][:rows]), np.ascontiguousarray(w["T0"][:rows]))
-    t0 = time.perf_counter()
-    o.step(1)
-    t1 = time.perf_counter()
-    n = max(1, int((seconds - (t1 - t0)) / max(t1 - t0, 1e-3)))
-    o.step(n)
-    t2 = time.perf_counter()
+    with oracle.thread_limit(threads):
+        used = oracle.threads()
+        t0 = time.perf_counter()
+        o.step(1)
+        t1 = time.perf_counter()
+        n = max(1, int((seconds - (t1 - t0)) / max(t1 - t0, 1e-3)))
+        o.step(n)
+        t2 = time.perf_counter()
     steps = n + 1
-    mlups = nx * rows * steps / (t2 - t0) / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle, rows 0-{rows - 1} of the {nx}x{p['ny']} workload "
-                      f"({nx * rows} sites incl. the bottom wall), {steps} steps, "
-                      f"{t2 - t0:.1f} s"}
+    return nx * rows * steps / (t2 - t0) / 1e6, used, steps, t2 - t0, rows
+
+
+def cpu_baseline(w, seconds=15.0):
+    """The FP64 oracle on the host cores, on bands of the same workload (the
+    lowest rows, full width, with the bottom wall): all threads for about
+    `seconds` on 512 rows, then one thread for about seconds / 2 on 64 rows;
+    MLUPS over each band's sites."""
+    nx, ny = w["params"]["nx"], w["params"]["ny"]
+    m_all, used, st_all, t_all, r_all = _oracle_band_mlups(w, 512, seconds)
+    m_one, _, st_one, t_one, r_one = _oracle_band_mlups(w, 64, seconds / 2, threads=1)
+    return {"value": round(m_all, 3), "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "single_thread": round(m_one, 3),
+            "sample": f"FP64 oracle on the {nx}x{ny} workload's lowest rows (bottom wall "
+                      f"included): rows 0-{r_all - 1} for {st_all} steps on {used} threads "
+                      f"({t_all:.1f} s), rows 0-{r_one - 1} for {st_one} steps on 1 thread "
+                      f"({t_one:.1f} s)"}
+
+
+# the oracle's step counts per workload: the full run where it is feasible,
+# else the first steps (the per-step cost does not change over a run)
+ORACLE_TABLE = (("poiseuille", 20000), ("planar_marangoni", 50000), ("droplet", 1000),
+                ("adjoint_droplet", 4000), ("multi_droplet", 20))
+
+
+def oracle_table(single_fraction=0.1):
+    """The FP64 oracle on each workload, on all host threads at the step
+    counts above and on one thread for single_fraction of them (at least one
+    step); prints one JSON line per run and a markdown table."""
+    from oracle import oracle
+    from paper_1412_6238_amd import workloads as wl
+    rows = []
+    for name, steps in ORACLE_TABLE:
+        w = wl.make(name)
+        p = w["params"]
+        n = p["nx"] * p["ny"]
+        for threads, nsteps in ((None, steps), (1, max(1, int(steps * single_fraction)))):
+            o = oracle.Oracle(p, w["Twall_bot"], w["Twall_top"])
+            o.init(w["phi0"], w["T0"])
+            with oracle.thread_limit(threads):
+                used = oracle.threads()
+                t0 = time.perf_counter()
+                o.step(nsteps)
+                dt = time.perf_counter() - t0
+            del o
+            r = {"workload": f"{name} {p['nx']}x{p['ny']}", "steps": nsteps, "threads": used,
+                 "seconds": round(dt, 2), "mlups": round(n * nsteps / dt / 1e6, 3)}
+            rows.append(r)
+            print(json.dumps(r), flush=True)
+    print("| workload | steps | threads | s | MLUPS |\n|---|---|---|---|---|")
+    for r in rows:
+        print(f"| {r['workload']} | {r['steps']} | {r['threads']} | {r['seconds']} | {r['mlups']} |")
 
 
 def adjoint_bench(args, torch, lbe_csf, wl):
@@ -150,7 +198,13 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of known size (for scaling HBM "
                          "byte counters) and exit")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="time only the FP64 oracle on every workload (all host threads, "
+                         "then one thread) and exit")
     args = ap.parse_args()
+    if args.oracle_table:
+        oracle_table()
+        return
     if args.calibrate_copy:
         import torch
         nbytes = 1 << 31
@@ -189,15 +243,22 @@ def main():
     sim.step(args.warmup)
     torch.cuda.synchronize()
 
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    # REPEATS timed windows of exactly --steps steps each, every window
+    # bracketed by a synchronisation, timed with HIP events on the handle's
+    # stream (where the step kernel runs); the median window is reported
+    windows = []
     t0 = time.perf_counter()
-    start.record(stream)
-    sim.step(args.steps)          # ends with one synchronising check of the diagnostics
-    stop.record(stream)
-    torch.cuda.synchronize()
+    for _ in range(REPEATS):
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        sim.step(args.steps)      # ends with one synchronising check of the diagnostics
+        stop.record(stream)
+        torch.cuda.synchronize()
+        windows.append(start.elapsed_time(stop))
     wall = time.perf_counter() - t0
-    ms = start.elapsed_time(stop)
+    ms = float(np.median(windows))
     ms_per_step = ms / args.steps
     mlups = sites * args.steps / (ms / 1e3) / 1e6
     hist = sim.diag_history()
@@ -205,15 +266,19 @@ def main():
     mass_drift = None
     if hist:
         mass_drift = d_last["mass"] / hist[0]["mass"] - 1.0
+    diag_in_windows = len([h for h in hist if h["step"] >= args.warmup])
 
-    # dominant kernel: the fused step; its average launch time over the timed
-    # region (the region also holds steps/diag_every tiny reduction launches)
+    # dominant kernel: the fused step, one launch per step; its average
+    # launch time is the window time over the steps (the window also holds
+    # one small reduction launch per diagnostic step)
     bps = BYTES_PER_SITE[args.precision]
+    stored = STORED_BYTES_PER_SITE[args.precision]
     if args.rho2 > 0:
-        # two densities: the pressure pass reads the 27 values (216 B in FP64,
-        # 116 B in the FP32 form) and writes the FP64 pressure of Eq. 9 (8 B),
-        # which the step then reads (8 B)
+        # two densities: the pressure pass reads the 27 values (half the
+        # step's bytes) and writes the FP64 pressure of Eq. 9 (8 B), which
+        # the step then reads (8 B)
         bps += bps // 2 + 8 + 8
+        stored += stored // 2 + 8 + 8
     achieved = bps * sites / (ms_per_step / 1e3) / 1e9
     traffic = (traffic_from_profile(args.workload, args.precision, sites, args.csf_form)
                if args.rho2 <= 0 else None)
@@ -234,15 +299,21 @@ def main():
                    "sites": sites, "diag_every": args.diag_every,
                    "capillary_form": "curvature" if args.csf_form == 1 else "potential",
                    "densities": [p["rho"], args.rho2] if args.rho2 > 0 else [p["rho"]],
-                   "bytes_per_site_update": bps},
+                   "bytes_per_site_update": bps, "stored_bytes_per_site_update": stored},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic},
+        "timing": {"windows": REPEATS, "steps_per_window": args.steps,
+                   "ms_per_step_each": [round(t / args.steps, 5) for t in windows],
+                   "statistic": "median window", "diag_steps_in_windows": diag_in_windows},
+        "stored_bytes_frac": round(stored * sites / (ms_per_step / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
         "wall_s": round(wall, 3),
         "mass_drift": mass_drift,
         "n_nonfinite": d_last["n_nonfinite"],
         "kernel_hash": kernel_hash(),
     }
+    if traffic:
+        out["traffic_over_algorithmic"] = round(traffic / (bps * sites), 4)
     if args.precision == "fp32_dev" and not args.no_error_check:
         # the FP32 form's error at this step count: the FP64 path run from the
         # same inputs for the same number of steps (outside the timed region)
@@ -251,12 +322,12 @@ def main():
         torch.cuda.empty_cache()
         ref = lbe_csf.Simulation(p, w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"],
                                  precision="fp64", diag_every=0)
-        ref.step(args.warmup + args.steps)
+        ref.step(args.warmup + REPEATS * args.steps)
         b = ref.fields()
         del ref
         rel = lambda x, y: float(torch.linalg.norm(x - y) / torch.linalg.norm(y))
         out["fp32_vs_fp64"] = {
-            "steps": args.warmup + args.steps,
+            "steps": args.warmup + REPEATS * args.steps,
             "phi": rel(a["phi"], b["phi"]),
             "u": rel(torch.stack([a["ux"], a["uy"]]), torch.stack([b["ux"], b["uy"]])),
             "T": rel(a["T"], b["T"]),

@@ -149,13 +149,25 @@ static double rho_of(const orc_params *P, double c) {
   return P->rho + c * (P->rho2 - P->rho);
 }
 
+/* Order of the sums over lattice directions in the moments and stencils:
+ * index order; a build with -DORC_REVERSED_SUMS sums in reverse order, the
+ * same arithmetic rounded differently, which the tests use only to measure
+ * how far two correct FP64 evaluations of an ill-conditioned case drift
+ * apart.  DIR(t, first) is the t-th direction of a loop starting at first. */
+#ifdef ORC_REVERSED_SUMS
+#define DIR(t, first) (NQ - 1 - (t) + (first))
+#else
+#define DIR(t, first) (t)
+#endif
+
 /* ---- pass A: moments of the pre-collision state --------------------------- */
 static void pass_moments(orc *o) {
   const int n = o->n;
 #pragma omp parallel for schedule(static)
   for (int s = 0; s < n; ++s) {
     double sf = 0.0, sg = 0.0, sh = 0.0, sx = 0.0, sy = 0.0;
-    for (int k = 0; k < NQ; ++k) {
+    for (int t = 0; t < NQ; ++t) {
+      const int k = DIR(t, 0);
       double fk = o->F[k * n + s];
       sf += fk;
       sx += OX[k] * fk;
@@ -182,7 +194,8 @@ static void stencil_site(const orc *o, const double *c, const double *T,
   const int s = j * o->P.wx + i;
   double gcx = 0, gcy = 0, lap = 0, gtx = 0, gty = 0, gpx = 0, gpy = 0;
   double hxx = 0, hxy = 0, hyy = 0;
-  for (int k = 1; k < NQ; ++k) {
+  for (int t = 1; t < NQ; ++t) {
+    const int k = DIR(t, 1);
     const int kind = o->nb_kind[k * o->n + s];
     const int loc = o->nb_loc[k * o->n + s];
     const int gcol = o->nb_col[k * o->n + s];
@@ -448,6 +461,18 @@ OAPI int orc_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
 #else
+  return 1;
+#endif
+}
+
+/* Set the number of OpenMP threads of later passes (n >= 1); results do not
+ * depend on it.  Returns the number in effect. */
+OAPI int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
   return 1;
 #endif
 }

@@ -44,27 +44,46 @@ class _Params(ctypes.Structure):
     ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (-O2 -ffp-contract=off, OpenMP)."""
+# Builds of the one source.  "" is the oracle (-ffp-contract=off: every
+# product and sum rounded as written).  "fma" lets the compiler fuse
+# multiply-adds and "rev" sums over the lattice directions in reverse order:
+# the same arithmetic with different rounding.  The tests use them only to
+# measure how far two correct FP64 evaluations drift apart on an
+# ill-conditioned case (the round-off floor of a comparison).
+VARIANTS = {"": ["-ffp-contract=off"], "fma": ["-ffp-contract=fast", "-mfma"],
+            "rev": ["-ffp-contract=off", "-DORC_REVERSED_SUMS"]}
+
+
+def lib_path(variant: str = "") -> str:
+    return LIB_PATH if not variant else os.path.join(_HERE, f"liblbe_oracle_{variant}.so")
+
+
+def build(verbose: bool = False, extra=(), variant: str = "") -> str:
+    """Compile the oracle with gcc (-O2, OpenMP; -ffp-contract=off for the
+    oracle itself)."""
     import subprocess
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", LIB_PATH, SRC_PATH, "-lm"]
+    out = lib_path(variant)
+    # written beside the library and renamed into place, so that processes
+    # that have the previous build loaded keep a consistent file
+    tmp = f"{out}.tmp{os.getpid()}"
+    cmd = ["gcc", "-O2", *VARIANTS[variant], "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-Wextra", *extra, "-o", tmp, SRC_PATH, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    return LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH) or (
-                os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH)):
-            build()
-        L = ctypes.CDLL(LIB_PATH)
+def lib(variant: str = ""):
+    if variant not in _libs:
+        path = lib_path(variant)
+        if not os.path.exists(path) or (os.path.getmtime(path) < os.path.getmtime(SRC_PATH)):
+            build(variant=variant)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_create.restype = ctypes.c_void_p
         L.orc_create.argtypes = [ctypes.POINTER(_Params), dp, dp]
@@ -80,9 +99,11 @@ def lib():
         L.orc_derived.argtypes = [ctypes.POINTER(_Params), dp]
         L.orc_sizeof_params.restype = ctypes.c_int
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         assert L.orc_sizeof_params() == ctypes.sizeof(_Params)
-        _lib = L
-    return _lib
+        _libs[variant] = L
+    return _libs[variant]
 
 
 def _ptr(a):
@@ -117,6 +138,24 @@ def threads() -> int:
     return int(lib().orc_threads())
 
 
+class thread_limit:
+    """Context manager: run the oracle's passes on n threads (None: leave
+    the count as it is); the previous count is restored on exit."""
+
+    def __init__(self, n=None):
+        self.n = n
+
+    def __enter__(self):
+        self.prev = threads()
+        if self.n is not None:
+            lib().orc_set_threads(int(self.n))
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_threads(self.prev)
+        return False
+
+
 def derived(p: dict) -> dict:
     out = np.zeros(4)
     lib().orc_derived(ctypes.byref(_make_params(p)), _ptr(out))
@@ -141,14 +180,16 @@ def collide_site(p: dict, pre27, stencil):
 class Oracle:
     """A grid (or a window of one) advanced by the plain FP64 oracle.
 
-    ``window=(x0, y0, wx, wy)`` holds only that part of the global domain;
+    ``variant="fma"`` runs the build with fused multiply-adds (for round-off
+floors only).  ``window=(x0, y0, wx, wy)`` holds only that part of the global domain;
     values whose dependence leaves the window come out as NaN.  Field arrays
     are (wy, wx) float64, x fastest.  The state is (27, wy, wx): f, g, hbar.
     """
 
     def __init__(self, params: dict, Twall_bot=None, Twall_top=None,
-                 window=None):
+                 window=None, variant: str = ""):
         self.params = dict(params)
+        self._lib = lib(variant)
         self.P = _make_params(params, window)
         self.wx, self.wy = self.P.wx, self.P.wy
         nx = self.P.NX
@@ -157,14 +198,14 @@ class Oracle:
         tt = np.ascontiguousarray(
             np.zeros(nx) if Twall_top is None else Twall_top, dtype=np.float64)
         assert tb.shape == (nx,) and tt.shape == (nx,)
-        self._h = lib().orc_create(ctypes.byref(self.P), _ptr(tb), _ptr(tt))
+        self._h = self._lib.orc_create(ctypes.byref(self.P), _ptr(tb), _ptr(tt))
         if not self._h:
             raise ValueError("oracle: invalid grid")
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_destroy(h)
+            self._lib.orc_destroy(h)
             self._h = None
 
     def _field(self, a):
@@ -173,37 +214,37 @@ class Oracle:
         return a
 
     def init(self, phi0, T0):
-        lib().orc_init(self._h, _ptr(self._field(phi0)), _ptr(self._field(T0)))
+        self._lib.orc_init(self._h, _ptr(self._field(phi0)), _ptr(self._field(T0)))
         return self
 
     def set_state(self, F):
         F = np.ascontiguousarray(F, dtype=np.float64)
         assert F.shape == (27, self.wy, self.wx)
-        lib().orc_set_state(self._h, _ptr(F))
+        self._lib.orc_set_state(self._h, _ptr(F))
         return self
 
     def state(self):
         F = np.zeros((27, self.wy, self.wx))
-        lib().orc_get_state(self._h, _ptr(F))
+        self._lib.orc_get_state(self._h, _ptr(F))
         return F
 
     def step(self, n: int = 1):
-        lib().orc_step(self._h, int(n))
+        self._lib.orc_step(self._h, int(n))
         return self
 
     def fields(self):
         out = [np.zeros((self.wy, self.wx)) for _ in range(5)]
-        lib().orc_fields(self._h, *[_ptr(a) for a in out])
+        self._lib.orc_fields(self._h, *[_ptr(a) for a in out])
         return dict(zip(("phi", "ux", "uy", "p", "T"), out))
 
     def intermediates(self):
         out = np.zeros((len(INTERMEDIATE_KEYS), self.wy, self.wx))
-        lib().orc_intermediates(self._h, _ptr(out))
+        self._lib.orc_intermediates(self._h, _ptr(out))
         return dict(zip(INTERMEDIATE_KEYS, out))
 
     def diag(self):
         d = np.zeros(N_DIAG)
-        lib().orc_diag(self._h, _ptr(d))
+        self._lib.orc_diag(self._h, _ptr(d))
         out = dict(zip(DIAG_KEYS, d))
         out["n_nonfinite"] = int(out["n_nonfinite"])
         out["centroid_y"] = out["sum_cy"] / out["mass"] if out["mass"] else float("nan")

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/lbe_csf.h"
 #include "adjoint.h"
@@ -287,59 +288,58 @@ void launch_mode(const Launch &la, const StepArgs &a, hipStream_t st) {
   }
 }
 
+// Launch the step kernel instantiated for this mode; false (nothing
+// launched) for a combination of mode bits that has no instantiation.
 template <typename S, typename R, bool DEV>
-void launch_prec(int mode, const Launch &la, const StepArgs &a, hipStream_t st) {
+bool launch_prec(int mode, const Launch &la, const StepArgs &a, hipStream_t st) {
   switch (mode) {
-    case kStore: launch_mode<S, R, DEV, kStore>(la, a, st); break;
-    case kStore | kDiag: launch_mode<S, R, DEV, kStore | kDiag>(la, a, st); break;
-    case kFields: launch_mode<S, R, DEV, kFields>(la, a, st); break;
-    case kDiag: launch_mode<S, R, DEV, kDiag>(la, a, st); break;
-    case kStore | kTape: launch_mode<S, R, DEV, kStore | kTape>(la, a, st); break;
-    case kTape: launch_mode<S, R, DEV, kTape>(la, a, st); break;
-    case kStore | kCurv: launch_mode<S, R, DEV, kStore | kCurv>(la, a, st); break;
-    case kStore | kDiag | kCurv: launch_mode<S, R, DEV, kStore | kDiag | kCurv>(la, a, st); break;
-    case kFields | kCurv: launch_mode<S, R, DEV, kFields | kCurv>(la, a, st); break;
-    case kDiag | kCurv: launch_mode<S, R, DEV, kDiag | kCurv>(la, a, st); break;
-    case kStore | kTape | kCurv: launch_mode<S, R, DEV, kStore | kTape | kCurv>(la, a, st); break;
-    case kTape | kCurv: launch_mode<S, R, DEV, kTape | kCurv>(la, a, st); break;
-    case kStore | kStream:
-    case kStore | kDiag | kStream:
-    case kStore | kCurv | kStream:
-    case kStore | kDiag | kCurv | kStream:
-      if constexpr (DEV) {
-        constexpr int T = kStream;
-        switch (mode) {
-          case kStore | T: launch_mode<S, R, DEV, kStore | T>(la, a, st); return;
-          case kStore | kDiag | T: launch_mode<S, R, DEV, kStore | kDiag | T>(la, a, st); return;
-          case kStore | kCurv | T: launch_mode<S, R, DEV, kStore | kCurv | T>(la, a, st); return;
-          default:
-            launch_mode<S, R, DEV, kStore | kDiag | kCurv | T>(la, a, st); return;
-        }
-      } else {
-        launch_prec<S, R, DEV>(mode & ~kStream, la, a, st);   // FP32 form only
-      }
-      break;
-    default: {
-      // two densities: the pressure pass, then the step
-      constexpr int V = kVarRho, P = kVarRho | kPress;
-      switch (mode) {
-        case P: launch_mode<S, R, DEV, P>(la, a, st); return;
-        case P | kCurv: launch_mode<S, R, DEV, P | kCurv>(la, a, st); return;
-        case V | kStore: launch_mode<S, R, DEV, V | kStore>(la, a, st); return;
-        case V | kStore | kDiag: launch_mode<S, R, DEV, V | kStore | kDiag>(la, a, st); return;
-        case V | kFields: launch_mode<S, R, DEV, V | kFields>(la, a, st); return;
-        case V | kDiag: launch_mode<S, R, DEV, V | kDiag>(la, a, st); return;
-        case V | kStore | kCurv: launch_mode<S, R, DEV, V | kStore | kCurv>(la, a, st); return;
-        case V | kStore | kDiag | kCurv:
-          launch_mode<S, R, DEV, V | kStore | kDiag | kCurv>(la, a, st); return;
-        case V | kFields | kCurv: launch_mode<S, R, DEV, V | kFields | kCurv>(la, a, st); return;
-        case V | kDiag | kCurv: launch_mode<S, R, DEV, V | kDiag | kCurv>(la, a, st); return;
-        default: break;
-      }
-      launch_mode<S, R, DEV, kFields | kDiag>(la, a, st);
-      break;
+    case kStore: launch_mode<S, R, DEV, kStore>(la, a, st); return true;
+    case kStore | kDiag: launch_mode<S, R, DEV, kStore | kDiag>(la, a, st); return true;
+    case kFields: launch_mode<S, R, DEV, kFields>(la, a, st); return true;
+    case kDiag: launch_mode<S, R, DEV, kDiag>(la, a, st); return true;
+    case kStore | kTape: launch_mode<S, R, DEV, kStore | kTape>(la, a, st); return true;
+    case kTape: launch_mode<S, R, DEV, kTape>(la, a, st); return true;
+    case kStore | kCurv: launch_mode<S, R, DEV, kStore | kCurv>(la, a, st); return true;
+    case kStore | kDiag | kCurv: launch_mode<S, R, DEV, kStore | kDiag | kCurv>(la, a, st); return true;
+    case kFields | kCurv: launch_mode<S, R, DEV, kFields | kCurv>(la, a, st); return true;
+    case kDiag | kCurv: launch_mode<S, R, DEV, kDiag | kCurv>(la, a, st); return true;
+    case kStore | kTape | kCurv: launch_mode<S, R, DEV, kStore | kTape | kCurv>(la, a, st); return true;
+    case kTape | kCurv: launch_mode<S, R, DEV, kTape | kCurv>(la, a, st); return true;
+    default: break;
+  }
+  if constexpr (DEV) {
+    // whole-line stores past the last-level cache (FP32 form, one density)
+    constexpr int T = kStream;
+    switch (mode) {
+      case kStore | T: launch_mode<S, R, DEV, kStore | T>(la, a, st); return true;
+      case kStore | kDiag | T: launch_mode<S, R, DEV, kStore | kDiag | T>(la, a, st); return true;
+      case kStore | kCurv | T: launch_mode<S, R, DEV, kStore | kCurv | T>(la, a, st); return true;
+      case kStore | kDiag | kCurv | T:
+        launch_mode<S, R, DEV, kStore | kDiag | kCurv | T>(la, a, st); return true;
+      default: break;
     }
   }
+  // two densities: the pressure pass, then the step
+  constexpr int V = kVarRho, P = kVarRho | kPress;
+  switch (mode) {
+    case P: launch_mode<S, R, DEV, P>(la, a, st); return true;
+    case P | kCurv: launch_mode<S, R, DEV, P | kCurv>(la, a, st); return true;
+    case V | kStore: launch_mode<S, R, DEV, V | kStore>(la, a, st); return true;
+    case V | kStore | kDiag: launch_mode<S, R, DEV, V | kStore | kDiag>(la, a, st); return true;
+    case V | kFields: launch_mode<S, R, DEV, V | kFields>(la, a, st); return true;
+    case V | kDiag: launch_mode<S, R, DEV, V | kDiag>(la, a, st); return true;
+    case V | kStore | kCurv: launch_mode<S, R, DEV, V | kStore | kCurv>(la, a, st); return true;
+    case V | kStore | kDiag | kCurv:
+      launch_mode<S, R, DEV, V | kStore | kDiag | kCurv>(la, a, st); return true;
+    case V | kFields | kCurv: launch_mode<S, R, DEV, V | kFields | kCurv>(la, a, st); return true;
+    case V | kDiag | kCurv: launch_mode<S, R, DEV, V | kDiag | kCurv>(la, a, st); return true;
+    default: return false;
+  }
+}
+
+bool launch_any(bool f64, int mode, const Launch &la, const StepArgs &a, hipStream_t st) {
+  return f64 ? launch_prec<double, double, false>(mode, la, a, st)
+             : launch_prec<float, float, true>(mode, la, a, st);
 }
 
 int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
@@ -359,17 +359,13 @@ int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
     // two densities: the pressure of Eq. 9 of the source state first (it
     // needs u, hence the force, at every site of the stencil)
     const int pm = kVarRho | kPress | (mode & kCurv);
-    if (h->P.precision == LBE_CSF_FP64)
-      launch_prec<double, double, false>(pm, h->la, a, h->stream);
-    else
-      launch_prec<float, float, true>(pm, h->la, a, h->stream);
+    if (!launch_any(h->P.precision == LBE_CSF_FP64, pm, h->la, a, h->stream))
+      return fail(h, LBE_CSF_EINVAL, "no step kernel for mode " + std::to_string(pm));
     HIPCHK(h, hipGetLastError());
     mode |= kVarRho;
   }
-  if (h->P.precision == LBE_CSF_FP64)
-    launch_prec<double, double, false>(mode, h->la, a, h->stream);
-  else
-    launch_prec<float, float, true>(mode, h->la, a, h->stream);
+  if (!launch_any(h->P.precision == LBE_CSF_FP64, mode, h->la, a, h->stream))
+    return fail(h, LBE_CSF_EINVAL, "no step kernel for mode " + std::to_string(mode));
   HIPCHK(h, hipGetLastError());
   return LBE_CSF_OK;
 }
@@ -687,12 +683,20 @@ int lbe_csf_diag_history(lbe_csf *h, lbe_csf_diag *out, int32_t max, int32_t *co
   const int64_t have = std::min<int64_t>(cnt[0], kDiagRing);
   const int64_t ncopy = std::min<int64_t>(have, std::max(0, max));
   const int64_t first = cnt[0] - have;
-  for (int64_t k = 0; k < ncopy; ++k) {
-    DiagRecord r;
-    HIPCHK(h, hipMemcpyAsync(&r, h->ring + ((first + k) % kDiagRing), sizeof(r),
+  if (ncopy > 0) {
+    // the oldest ncopy records: one contiguous range of the ring, or two
+    // when it wraps
+    std::vector<DiagRecord> buf((size_t)ncopy);
+    const int64_t start = first % kDiagRing;
+    const int64_t part1 = std::min<int64_t>(ncopy, kDiagRing - start);
+    HIPCHK(h, hipMemcpyAsync(buf.data(), h->ring + start, (size_t)part1 * sizeof(DiagRecord),
                              hipMemcpyDeviceToHost, h->stream));
+    if (part1 < ncopy)
+      HIPCHK(h, hipMemcpyAsync(buf.data() + part1, h->ring,
+                               (size_t)(ncopy - part1) * sizeof(DiagRecord),
+                               hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    to_public(r, &out[k]);
+    for (int64_t k = 0; k < ncopy; ++k) to_public(buf[(size_t)k], &out[k]);
   }
   *count = (int32_t)ncopy;
   int64_t zero[2] = {0, cnt[1]};

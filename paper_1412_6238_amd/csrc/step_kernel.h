@@ -338,9 +338,6 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     const R src_h = R(3) * irho;              // 1 / (rho cs^2)
     const bool walls = a.walls_y != 0;
     const bool bot = walls && j == 0, top = walls && j == ny - 1;
-    R gsum = 0;                                // sum of g_1..8 = c - g_0
-#pragma unroll
-    for (int q = 1; q < 9; ++q) gsum += cur.v[9 + q];
     const uint32_t s_own = (uint32_t)(j * nx + x);
     auto st = [&](int q, uint32_t off, R val) {
       buf_store<S>(S(val), rd, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes);
@@ -457,10 +454,11 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       gnew = cur.g0() + double(dg);
       hnew = cur.h0() + double(dh);
     } else {
-      // g^eq_0 - g_0 = sum_{q>0} g_q - (1 - w0) 3 Gamma mu + c G_0
-      const R w0 = wq<R>(0);
-      const R d0 = gsum - (R(1) - w0) * gmu + c * G0;
-      gnew = cur.g0() + double(wg * d0 + gsrc0);
+      // Eqs. 12-14 as printed: g_0 - w_g (g_0 - g^eq_0) with
+      // g^eq_0 = c - (1 - w0) 3 Gamma mu + c G_0 and c = sum g
+      const double w0 = wq<double>(0);
+      const double geq0 = cd - (1.0 - w0) * double(gmu) + cd * double(G0);
+      gnew = cur.g0() - double(wg) * (cur.g0() - geq0) + double(gsrc0);
       const double hdiff = cur.h0() - rcv_s * Tfull_d * double(gam0);
       hnew = cur.h0() + double(-wT * R(hdiff) + hsrc0);
     }

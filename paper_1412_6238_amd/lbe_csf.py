@@ -7,7 +7,10 @@ raises if the library has not been built (``python -m
 paper_1412_6238_amd.build``); there is no fallback path.
 
 The functions keep the C names (``lbe_csf_create``, ``lbe_csf_step``, ...);
-``Simulation`` bundles a handle with the tensors it borrows.
+``Simulation`` bundles a handle with the tensors it borrows.  Two
+``torch.autograd.Function`` wrappers differentiate a recorded run through
+lbe_csf_backward: ``CSFDroplet`` (the droplet migration J, Sec. IV C) and
+``LbeRun`` (the final order-parameter field).
 """
 from __future__ import annotations
 
@@ -265,6 +268,52 @@ class LbeRun(torch.autograd.Function):
     def backward(ctx, dphi):
         sim = ctx.sim
         g = sim.backward(2.0 * dphi.detach().to(torch.float64), want_F0=False, want_T0=True)
+        ctx.sim = None
+        dsT = torch.tensor(g["sigmaT"], dtype=torch.float64, device=ctx.sT_device)
+        dtb = g["Twall"][0] if ctx.has_walls else None
+        dtt = g["Twall"][1] if ctx.has_walls else None
+        return dsT, dtb, dtt, g["T0"], None, None, None, None
+
+
+class CSFDroplet(torch.autograd.Function):
+    """Droplet migration J = y_c(N) - y_c(0) of an N-step run, y_c = sum c y /
+    sum c the centroid of the order parameter (Sec. IV C, unthresholded so
+    that J is differentiable), as a differentiable function of sigmaT, the
+    wall temperatures and the initial temperature field.
+
+    ``apply(sigmaT, Twall_bot, Twall_top, T0, params, phi0, nsteps, precision)``
+    returns a 0-d FP64 tensor on the device of T0.  Forward: a recorded run in
+    the library; the centroids are the library's FP64 diagnostics.  Backward:
+    lbe_csf_backward with the seed dJ/dc_N = (y - y_c(N)) / sum c_N, giving
+    dJ/dsigmaT, the direct wall derivatives and dJ/dT0.  When T0 is itself a
+    function of the walls (a conduction profile computed with torch ops),
+    autograd adds the path through T0 to the wall gradients.
+    """
+
+    @staticmethod
+    def forward(ctx, sigmaT, Twall_bot, Twall_top, T0, params, phi0, nsteps, precision):
+        p = dict(params)
+        p["sigmaT"] = float(sigmaT.detach().cpu())
+        nsteps = int(nsteps)
+        dev = T0.device if T0.is_cuda else torch.device("cuda:0")
+        sim = Simulation(p, phi0, T0.detach(), None if Twall_bot is None else Twall_bot.detach(),
+                         None if Twall_top is None else Twall_top.detach(), precision=precision,
+                         record_steps=nsteps, device=dev)
+        y0 = sim.diagnostics()["centroid_y"]
+        sim.step(nsteps, record=True)
+        d = sim.diagnostics()
+        ctx.sim, ctx.yN, ctx.mass = sim, d["centroid_y"], d["mass"]
+        ctx.has_walls = Twall_bot is not None
+        ctx.sT_device = sigmaT.device
+        return torch.tensor(d["centroid_y"] - y0, dtype=torch.float64, device=dev)
+
+    @staticmethod
+    def backward(ctx, dJ):
+        sim = ctx.sim
+        y = torch.arange(sim.ny, dtype=torch.float64, device=sim.device)[:, None] + 0.5
+        seed = ((y - ctx.yN) / ctx.mass).expand(sim.ny, sim.nx) * dJ.to(sim.device)
+        # the seed carries the incoming gradient, so every output does too
+        g = sim.backward(seed.contiguous(), want_F0=False, want_T0=True)
         ctx.sim = None
         dsT = torch.tensor(g["sigmaT"], dtype=torch.float64, device=ctx.sT_device)
         dtb = g["Twall"][0] if ctx.has_walls else None

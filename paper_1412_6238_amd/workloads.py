@@ -165,6 +165,18 @@ def conduction_field_T(G, ny):
     return np.fft.irfft(np.fft.rfft(G, axis=1) * B, n=nx, axis=1).sum(axis=0)
 
 
+def conduction_field_torch(Tw_bot, T_top, ny):
+    """``conduction_field`` written with torch operations on the wall tensor's
+    device and dtype, so that autograd carries gradients of T0 back to Tw_bot
+    (the transpose of this linear map)."""
+    import torch
+    nx = Tw_bot.shape[0]
+    B = torch.as_tensor(_conduction_kernel(nx, ny), dtype=Tw_bot.dtype, device=Tw_bot.device)
+    T = torch.fft.irfft(torch.fft.rfft(Tw_bot)[None, :] * B, n=nx, dim=1)
+    y = torch.arange(ny, dtype=Tw_bot.dtype, device=Tw_bot.device) + 0.5
+    return T + (T_top * y / ny)[:, None]
+
+
 # ---- the workloads -----------------------------------------------------------
 def _droplet_physics(**kw):
     # eta = 0.0715542, lambda = 7.15542e-3: Re = 1 and Ma = 10 for R = 32,

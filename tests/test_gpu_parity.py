@@ -138,17 +138,19 @@ def test_fp64_diagnostics(lbe, oracle_mod):
 
 
 @pytest.mark.parametrize("name,nsteps,p0", [("poiseuille", 20000, 1 / 3),
-                                            ("planar_marangoni", 5000, 0.0),
-                                            ("droplet", 60, 0.0), ("adjoint_droplet", 1000, 0.0)])
+                                            ("planar_marangoni", 50000, 0.0),
+                                            ("droplet", 1000, 0.0), ("adjoint_droplet", 4000, 0.0)])
 def test_fp64_workloads(lbe, oracle_mod, name, nsteps, p0):
-    """The workloads at oracle-feasible step counts.  Droplet and planar cases
+    """The workloads at their stated step counts (the 512 x 1024 droplet at
+    its first 1,000 of 100,000).  Droplet and planar cases
     run in the p0 = 0 gauge (an exact symmetry of the method): at p0 = 1/3 the
     populations are ~1e4 times the velocity they encode and the FP64
     round-off of u alone approaches 1e-12.  The planar case is weaker still:
     its Marangoni flow (|u| ~ 1e-6) is the small residue of capillary terms of
     size ~1e-1 that cancel in mu, so its velocity is compared against the
-    oracle's own round-off floor, measured by re-running the oracle from an
-    initial state perturbed at the 1e-16 level."""
+    round-off floor of the comparison itself: the oracle against the same
+    oracle source compiled with fused multiply-adds, after the same steps
+    (GPU within ten times that)."""
     w = wl.make(name, p0=p0)
     _say(f"case workload {name} fp64 {nsteps} steps p0={p0:.3f}")
     sim, orc = _pair(lbe, oracle_mod, w)
@@ -159,9 +161,10 @@ def test_fp64_workloads(lbe, oracle_mod, name, nsteps, p0):
     g["p"] = g["p"] + (1 / 3 - p0)
     o["p"] = o["p"] + (1 / 3 - p0)
     if name == "planar_marangoni":
-        rng = np.random.default_rng(0)
-        phi_b = w["phi0"] * (1 + 2e-16 * rng.choice([-1.0, 1.0], w["phi0"].shape))
-        ob = oracle_mod.Oracle(w["params"], w["Twall_bot"], w["Twall_top"]).init(phi_b, w["T0"])
+        # the floor: the same oracle source built with fused multiply-adds
+        # (the GPU's kind of rounding), against the oracle
+        ob = oracle_mod.Oracle(w["params"], w["Twall_bot"], w["Twall_top"], variant="fma")
+        ob.init(w["phi0"], w["T0"])
         ob.step(nsteps)
         fb = ob.fields()
         floor = _rel(np.stack([fb["ux"], fb["uy"]]), np.stack([o["ux"], o["uy"]]))
@@ -197,11 +200,11 @@ def test_row_pipelines_agree(lbe, oracle_mod, monkeypatch, pipe, precision):
         _cmp({"F": F}, {"F": orc.state()}, what="F")
 
 
-@pytest.mark.parametrize("extra", [{}, {"csf_form": 1}, {"rho2": 2.0}])
+@pytest.mark.parametrize("extra", [{}, {"csf_form": 1}])
 def test_fp32_store_policy_does_not_matter(lbe, monkeypatch, extra):
     """The FP32 form's whole-line stores with and without the cache bypass
     (chosen by state size; forced both ways here) give the same state, bit
-    for bit."""
+    for bit.  (The two-density step has no bypass variant.)"""
     case = wl.random_case(136, 40, seed=31, walls_y=1)
     p = dict(case["params"], **extra)
     out = []
@@ -243,6 +246,26 @@ def test_determinism(lbe):
     np.testing.assert_array_equal(res[0][0], res[1][0])
     assert res[0][1] == res[1][1]
     assert [r["step"] for r in res[0][1]] == [0, 10, 20, 30, 40]
+
+
+def test_diag_history_wraps(lbe):
+    """The device keeps the last 4096 diagnostic records: after 4200 steps with
+    a record every step, lbe_csf_diag_history returns steps 104-4199 in order
+    (the ring wrapped), or the oldest `max` of them, and then starts over."""
+    case = wl.random_case(8, 8, seed=3, walls_y=1)
+    _say("case diag ring 8x8, 4200 steps, every step")
+    sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                         case["Twall_top"], diag_every=1)
+    sim.step(4200)
+    last = sim.diagnostics()
+    h = sim.diag_history(4096)
+    assert [r["step"] for r in h] == list(range(104, 4200))
+    assert all(r["n_nonfinite"] == 0 for r in h)
+    assert abs(h[-1]["mass"] / last["mass"] - 1.0) < 1e-12
+    sim.step(10)
+    h2 = sim.diag_history(4)
+    assert [r["step"] for r in h2] == [4200, 4201, 4202, 4203]
+    assert sim.diag_history(4096) == []
 
 
 def test_nonfinite_is_reported(lbe):
@@ -343,7 +366,7 @@ def test_full_size_sampled(lbe, oracle_mod, precision, tol):
     w = wl.make("multi_droplet")
     p = w["params"]
     nx, ny = p["nx"], p["ny"]
-    k = 3
+    k = 20
     _say(f"case full-size multi_droplet {precision} {k} steps")
     sim = lbe.Simulation(p, w["phi0"], w["T0"], w["Twall_bot"], w["Twall_top"], precision=precision)
     sim.step(k)

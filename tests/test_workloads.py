@@ -94,3 +94,22 @@ def test_generators_are_seeded():
     np.testing.assert_array_equal(wl.random_state(20, 10, 3), wl.random_state(20, 10, 3))
     np.testing.assert_array_equal(wl.make("adjoint_droplet")["Twall_bot"],
                                   wl.make("adjoint_droplet")["Twall_bot"])
+
+
+def test_conduction_field_torch_and_its_transpose():
+    """The torch form of the conduction field equals the numpy form, and
+    autograd through it equals conduction_field_T (the transpose the wall
+    gradient of the differentiated run needs)."""
+    import torch
+    rng = np.random.default_rng(11)
+    nx, ny = 48, 30
+    tb = rng.normal(0.0, 0.1, nx)
+    a = wl.conduction_field(tb, 2.5, ny)
+    t = torch.tensor(tb, requires_grad=True)
+    b = wl.conduction_field_torch(t, 2.5, ny)
+    assert np.abs(a - b.detach().numpy()).max() <= 1e-14
+    G = rng.normal(size=(ny, nx))
+    (b * torch.tensor(G)).sum().backward()
+    assert np.abs(t.grad.numpy() - wl.conduction_field_T(G, ny)).max() <= 1e-13
+    # the field solves the discrete boundary values: rows approach the walls
+    assert np.abs(b.detach().numpy()[-1] - 2.5).max() < 0.1

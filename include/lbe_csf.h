@@ -178,6 +178,18 @@ LBE_CSF_API int lbe_csf_fields(lbe_csf *h, double *phi, double *ux, double *uy, 
 /* Diagnostics of the current state (synchronises the stream). */
 LBE_CSF_API int lbe_csf_diagnostics(lbe_csf *h, lbe_csf_diag *out);
 
+/* The diagnostics of lbe_csf_diagnostics, computed without any device memory
+ * beyond the handle's state: for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The per-block partial sums and the record live in a static device array
+ * of the library (one per GPU, about 0.9 MB, held until the process ends):
+ * at most 16384 blocks per diagnostic launch, else EINVAL with a message.
+ * Calls on one GPU share that array: calls that overlap on one GPU (from
+ * other threads or streams) race and must be serialised by the caller.
+ * Makes the handle's device current for the call and restores the caller's.
+ * Synchronises the stream.  Errors: EINVAL, EDEVICE. */
+LBE_CSF_API int lbe_csf_diagnostics_noalloc(lbe_csf *h, lbe_csf_diag *out);
+
 /* Copy up to max records taken during lbe_csf_step (oldest first, the device
  * keeps the last 4096) into host out; *count receives the number copied.
  * Clears the history.  Synchronises the stream. */

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -204,6 +205,7 @@ struct lbe_csf {
   int64_t rec_start, rec_steps, rec_K;
   std::string err;
   StepArgs base;      // constants filled once
+  int device;         // the HIP device current at creation
 };
 
 namespace {
@@ -343,8 +345,10 @@ bool launch_any(bool f64, int mode, const Launch &la, const StepArgs &a, hipStre
 }
 
 int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
-                double *ux, double *uy, double *p, double *T, void *tape = nullptr) {
+                double *ux, double *uy, double *p, double *T, void *tape = nullptr,
+                double *partials = nullptr) {
   StepArgs a = h->base;
+  if (partials) a.partials = partials;
   a.src = src;
   a.dst = dst;
   a.tape = tape;
@@ -501,6 +505,41 @@ void to_public(const DiagRecord &r, lbe_csf_diag *o) {
   o->n_nonfinite = (int64_t)r.v[6];
 }
 
+// Scratch of lbe_csf_diagnostics_noalloc: the per-block partial sums of one
+// diagnostic launch, then one record.  A file-scope device array, so that the
+// call needs no device memory from the caller or the runtime; every GPU the
+// library runs on holds its own copy until the process ends.  Host code uses
+// only the address that hipGetSymbolAddress returns for the current device
+// (the array's name is not a device address on the host).
+constexpr int kScratchMaxBlocks = 16384;
+constexpr size_t kScratchDoubles =
+    (size_t)kScratchMaxBlocks * kNumPartials + (sizeof(DiagRecord) + 7) / 8;
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch array (looked up once per device, with
+// that device current); nullptr and a message on failure.
+double *scratch_on(int device, std::string *why) {
+  if (device < 0 || device >= kMaxDevices) {
+    *why = "device ordinal out of range";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[device] = static_cast<double *>(ptr);
+  }
+  return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 extern "C" {
@@ -549,6 +588,7 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
       h->la.stream = v == 1 && params->precision == LBE_CSF_FP32_DEV && !two_densities(params);
   }
   h->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
   h->ws = static_cast<char *>(workspace);
   h->state[0] = h->ws + L.off_a;
   h->state[1] = h->ws + L.off_b;
@@ -672,6 +712,46 @@ int lbe_csf_diagnostics(lbe_csf *h, lbe_csf_diag *out) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   to_public(r, out);
   return LBE_CSF_OK;
+}
+
+int lbe_csf_diagnostics_noalloc(lbe_csf *h, lbe_csf_diag *out) {
+  if (!h || !out) return h ? fail(h, LBE_CSF_EINVAL, "out is NULL") : LBE_CSF_EINVAL;
+  if (h->la.nblocks > kScratchMaxBlocks)
+    return fail(h, LBE_CSF_EINVAL,
+                "diagnostics_noalloc: the launch has " + std::to_string(h->la.nblocks) +
+                    " blocks, the static scratch holds the partials of at most " +
+                    std::to_string(kScratchMaxBlocks));
+  int prev = 0;
+  HIPCHK(h, hipGetDevice(&prev));
+  if (prev != h->device) HIPCHK(h, hipSetDevice(h->device));
+  std::string why;
+  double *ptr = scratch_on(h->device, &why);
+  int rc = LBE_CSF_OK;
+  if (!ptr) {
+    rc = fail(h, LBE_CSF_EDEVICE, why);
+  } else {
+    // every block writes its own partials and the reduction writes the
+    // record, so nothing needs clearing first
+    double *partials = ptr;
+    DiagRecord *rec = reinterpret_cast<DiagRecord *>(ptr + (size_t)kScratchMaxBlocks * kNumPartials);
+    rc = launch_step(h, kDiag, h->state[h->cur], nullptr, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, partials);
+    if (rc == LBE_CSF_OK) {
+      diag_reduce_kernel<<<1, 256, 0, h->stream>>>(partials, h->la.nblocks, rec, 1, nullptr,
+                                                   h->step);
+      DiagRecord r;
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&r, rec, sizeof(r), hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess)
+        rc = fail(h, LBE_CSF_EDEVICE, std::string("diagnostics_noalloc: ") + hipGetErrorString(e));
+      else
+        to_public(r, out);
+    }
+  }
+  if (prev != h->device) (void)hipSetDevice(prev);
+  return rc;
 }
 
 int lbe_csf_diag_history(lbe_csf *h, lbe_csf_diag *out, int32_t max, int32_t *count) {

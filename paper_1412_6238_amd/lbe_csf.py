@@ -40,7 +40,8 @@ LBE_CSF_FP64, LBE_CSF_FP32_DEV = 0, 1
 PRECISIONS = {"fp64": LBE_CSF_FP64, "fp32_dev": LBE_CSF_FP32_DEV}
 
 EXPORTED = ("lbe_csf_workspace_size", "lbe_csf_create", "lbe_csf_step", "lbe_csf_fields",
-            "lbe_csf_diagnostics", "lbe_csf_diag_history", "lbe_csf_get_state",
+            "lbe_csf_diagnostics", "lbe_csf_diagnostics_noalloc", "lbe_csf_diag_history",
+            "lbe_csf_get_state",
             "lbe_csf_set_state", "lbe_csf_step_count", "lbe_csf_backward", "lbe_csf_destroy",
             "lbe_csf_strerror", "lbe_csf_last_error")
 
@@ -83,6 +84,7 @@ _sig = {
     "lbe_csf_step": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32]),
     "lbe_csf_fields": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "lbe_csf_diagnostics": (ctypes.c_int, [_vp, ctypes.POINTER(lbe_csf_diag)]),
+    "lbe_csf_diagnostics_noalloc": (ctypes.c_int, [_vp, ctypes.POINTER(lbe_csf_diag)]),
     "lbe_csf_diag_history": (ctypes.c_int, [_vp, ctypes.POINTER(lbe_csf_diag), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
     "lbe_csf_get_state": (ctypes.c_int, [_vp, _vp]),
@@ -202,6 +204,13 @@ class Simulation:
     def diagnostics(self):
         d = lbe_csf_diag()
         _check(lbe_csf_diagnostics(self.h, ctypes.byref(d)), self.h)
+        return d.as_dict()
+
+    def diagnostics_noalloc(self):
+        """lbe_csf_diagnostics_noalloc: the same values, scratch in the
+        library's static device array."""
+        d = lbe_csf_diag()
+        _check(lbe_csf_diagnostics_noalloc(self.h, ctypes.byref(d)), self.h)
         return d.as_dict()
 
     def diag_history(self, max_records=4096):

@@ -24,7 +24,7 @@ def binding():
 
 def test_every_declared_symbol_is_exported(binding):
     names = _declared()
-    assert len(names) == 13, names
+    assert len(names) == 14, names
     lib = ctypes.CDLL(binding.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n

@@ -1,0 +1,74 @@
+"""lbe_csf_diagnostics_noalloc (the entry point that allocates nothing: its
+scratch is a static device array of the library) against lbe_csf_diagnostics,
+through the C ABI: two calls in a row, the second on a smaller grid, and a
+launch too large for the static scratch rejected on the host."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1412_6238_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("mass", "energy", "sum_cy", "sum_cx", "mass_thr", "sum_cuy_thr", "centroid_y", "u_r")
+
+
+@pytest.fixture(scope="module")
+def lbe():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1412_6238_amd import lbe_csf
+    return lbe_csf
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _both(lbe, sim):
+    ref = lbe.lbe_csf_diag()
+    got = lbe.lbe_csf_diag()
+    assert lbe.lbe_csf_diagnostics(sim.h, ctypes.byref(ref)) == lbe.LBE_CSF_OK
+    assert lbe.lbe_csf_diagnostics_noalloc(sim.h, ctypes.byref(got)) == lbe.LBE_CSF_OK
+    return ref.as_dict(), got.as_dict()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
+def test_noalloc_diagnostics_match(lbe, precision):
+    sizes = [(300, 200, 7), (40, 24, 5)]   # the second call on a smaller grid
+    for nx, ny, steps in sizes:
+        _say(f"case noalloc diagnostics {nx}x{ny} {precision} {steps} steps")
+        case = wl.random_case(nx, ny, seed=nx + ny, walls_y=1)
+        sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                             case["Twall_top"], precision=precision)
+        sim.step(steps)
+        ref, got = _both(lbe, sim)
+        assert got["step"] == ref["step"] == steps
+        assert got["n_nonfinite"] == ref["n_nonfinite"] == 0
+        for k in KEYS:
+            # the same kernels and the same fixed-order reduction
+            assert got[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-15), (nx, ny, k)
+        sim.step(2)
+        ref, got = _both(lbe, sim)
+        for k in KEYS:
+            assert got[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-15), (nx, ny, k)
+
+
+def test_noalloc_rejects_launch_beyond_scratch(lbe, monkeypatch):
+    """One-row chunks on a tall grid make 20,000 blocks, more partials than
+    the static scratch holds: EINVAL with a message, nothing launched."""
+    monkeypatch.setenv("LBE_CSF_ROWS", "1")
+    nx, ny = 64, 20000
+    case = wl.random_case(nx, ny, seed=4, walls_y=1, n_drops=1)
+    _say(f"case noalloc over the limit {nx}x{ny}")
+    sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                         case["Twall_top"], precision="fp32_dev")
+    with pytest.raises(lbe.LbeCsfError) as e:
+        sim.diagnostics_noalloc()
+    assert e.value.status == lbe.LBE_CSF_EINVAL
+    assert "static scratch" in str(e.value)
+    # the ordinary call still works on the same handle
+    assert sim.diagnostics()["n_nonfinite"] == 0

@@ -43,7 +43,7 @@ PARAM_KEYS = ("nx", "ny", "walls_y", "rho", "cv", "tau_f", "tau_T", "tau_g",
               "p0", "T_shift", "T_grad", "csf_form")
 
 WORKLOADS = ("poiseuille", "planar_marangoni", "droplet", "adjoint_droplet",
-             "multi_droplet")
+             "multi_droplet", "adjoint_droplet_wide")
 
 
 def base_params(nx: int, ny: int, **kw) -> dict:
@@ -229,6 +229,20 @@ def make(name: str, **overrides) -> dict:
         tt = np.full(nx, 0.01 * ny)
         T0 = conduction_field(tb, tt[0], ny)
         nsteps, prec = 4000, "fp32_dev"
+    elif name == "adjoint_droplet_wide":
+        # the differentiated run at a size where HBM bandwidth is the bound:
+        # 4096 x 1024, sixteen droplets of radius 24 a row above the bottom
+        # wall (as in adjoint_droplet), bottom wall N(0, 0.1^2), T0 the
+        # conduction field of the walls; 400 steps (20 checkpoints)
+        nx, ny = 4096, 1024
+        p = base_params(nx, ny, T_shift=0.0, T_grad=0.01, **_droplet_physics())
+        drops = [(128.0 + 256.0 * k, 96.0, 24.0) for k in range(16)]
+        phi0 = droplet_phi(nx, ny, drops, W_DEFAULT)
+        rng = np.random.default_rng(62380)
+        tb = 0.0 + rng.normal(0.0, 0.1, nx)
+        tt = np.full(nx, 0.01 * ny)
+        T0 = conduction_field(tb, tt[0], ny)
+        nsteps, prec = 400, "fp32_dev"
     elif name == "multi_droplet":
         nx, ny = 4096, 4096
         p = base_params(nx, ny, T_shift=0.0, T_grad=0.002, **_droplet_physics())

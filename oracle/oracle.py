@@ -51,7 +51,11 @@ class _Params(ctypes.Structure):
 # measure how far two correct FP64 evaluations drift apart on an
 # ill-conditioned case (the round-off floor of a comparison).
 VARIANTS = {"": ["-ffp-contract=off"], "fma": ["-ffp-contract=fast", "-mfma"],
-            "rev": ["-ffp-contract=off", "-DORC_REVERSED_SUMS"]}
+            "rev": ["-ffp-contract=off", "-DORC_REVERSED_SUMS"],
+            # the oracle itself under AddressSanitizer and UndefinedBehaviorSanitizer
+            # (tests/test_sanitizers.py loads it with the ASan runtime preloaded)
+            "asan": ["-ffp-contract=off", "-g", "-fno-omit-frame-pointer",
+                     "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]}
 
 
 def lib_path(variant: str = "") -> str:
@@ -156,13 +160,13 @@ class thread_limit:
         return False
 
 
-def derived(p: dict) -> dict:
+def derived(p: dict, variant: str = "") -> dict:
     out = np.zeros(4)
-    lib().orc_derived(ctypes.byref(_make_params(p)), _ptr(out))
+    lib(variant).orc_derived(ctypes.byref(_make_params(p)), _ptr(out))
     return dict(eps=out[0], alpha=out[1], kcap=out[2], Gamma=out[3])
 
 
-def collide_site(p: dict, pre27, stencil):
+def collide_site(p: dict, pre27, stencil, variant: str = ""):
     """Single-site collision: returns (post[27], aux dict).  ``stencil`` holds
     (gcx, gcy, lapc, gTx, gTy, gpx, gpy) and optionally the Hessian of c
     (hxx, hxy, hyy), which only the curvature form reads (zeros if absent)."""
@@ -171,7 +175,7 @@ def collide_site(p: dict, pre27, stencil):
     st[:len(stencil)] = np.asarray(stencil, dtype=np.float64)
     out = np.zeros(27)
     aux = np.zeros(11)
-    lib().orc_collide_site(ctypes.byref(_make_params(p)), _ptr(pre), _ptr(st),
+    lib(variant).orc_collide_site(ctypes.byref(_make_params(p)), _ptr(pre), _ptr(st),
                            _ptr(out), _ptr(aux))
     keys = ("c", "T", "p", "mu", "Fx", "Fy", "ux", "uy", "wf", "wT", "wg")
     return out, dict(zip(keys, aux))

@@ -38,62 +38,6 @@
 
 namespace lbe {
 
-constexpr int kAdjTX = 64;   // adjoint tile: 64 columns x 4 rows, one site per thread
-constexpr int kAdjTY = 4;
-// stencil cotangent planes: grad c, lap c, grad T, grad p, and the Hessian of
-// c (hxx, hxy, hyy; read by the curvature form only)
-constexpr int kAdjA = 10;
-
-struct AdjLayout {
-  int64_t record_steps;   // capacity N
-  int64_t K;              // checkpoint spacing for N steps
-  int64_t nchk;           // checkpoints ceil(N / K)
-  size_t state_bytes;     // one state (aligned)
-  size_t mom_bytes;       // one moment set: c (FP64), T, p, jx, jy
-  size_t plane_bytes;     // one plane of the arithmetic type
-  size_t off_chk;         // nchk states
-  size_t off_tape;        // K states, then K moment sets
-  size_t off_lam;         // D x2 (27 planes), M x2 (3 planes), A (kAdjA planes)
-  size_t off_part;        // per-block FP64 partial sums of dJ/dsigmaT
-  size_t off_tw;          // FP64 [2][nx] dJ/dTwall accumulators
-  size_t off_out;         // FP64 scalar result
-  size_t total;
-};
-
-inline int64_t adj_segment_length(int64_t nsteps) {
-  if (nsteps <= 1) return 1;
-  int64_t K = (int64_t)std::ceil(std::sqrt((double)nsteps));
-  while (K * K < nsteps) ++K;
-  while (K > 1 && (K - 1) * (K - 1) >= nsteps) --K;
-  return K;
-}
-
-inline int adj_tiles_x(int nx) { return (nx + kAdjTX - 1) / kAdjTX; }
-inline int adj_tiles_y(int ny) { return (ny + kAdjTY - 1) / kAdjTY; }
-
-inline AdjLayout adj_layout(int nx, int ny, size_t state_bytes, size_t value_bytes,
-                            int64_t record_steps) {
-  AdjLayout A{};
-  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-  A.record_steps = record_steps;
-  if (record_steps <= 0) return A;
-  const size_t n = (size_t)nx * ny;
-  A.state_bytes = al(state_bytes);
-  A.mom_bytes = al(n * (8 + 4 * value_bytes));
-  A.plane_bytes = al(n * value_bytes);
-  A.K = adj_segment_length(record_steps);
-  A.nchk = (record_steps + A.K - 1) / A.K;
-  size_t o = 0;
-  A.off_chk = o; o += (size_t)A.nchk * A.state_bytes;
-  A.off_tape = o; o += (size_t)A.K * (A.state_bytes + A.mom_bytes);
-  A.off_lam = o; o += (2 * 27 + 2 * 3 + kAdjA) * A.plane_bytes;
-  A.off_part = o; o += al((size_t)adj_tiles_x(nx) * adj_tiles_y(ny) * sizeof(double));
-  A.off_tw = o; o += al(2 * (size_t)nx * sizeof(double));
-  A.off_out = o; o += 256;
-  A.total = o;
-  return A;
-}
-
 inline int adj_save_checkpoint(char *adj_base, const AdjLayout &A, int64_t k,
                                const void *state, size_t bytes, hipStream_t st) {
   if (k < 0 || k >= A.nchk) return 1;

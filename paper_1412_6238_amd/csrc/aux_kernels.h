@@ -63,11 +63,7 @@ init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
 }
 
 // Deterministic final reduction of the per-block partials into one record,
-// appended to a device ring of records.
-struct DiagRecord {
-  int64_t step;
-  double v[kNumPartials];
-};
+// appended to a device ring of records (DiagRecord, host_layout.h).
 
 __global__ void __launch_bounds__(256)
 diag_reduce_kernel(const double *__restrict__ partials, int nblocks,

@@ -1,0 +1,263 @@
+// host_layout.h -- host-side logic of liblbe_csf without HIP: the sizes of a
+// state, the caller's workspace layout, the launch shape of the step kernel
+// and the parameter checks.  The library includes it; so does a CPU test
+// driver built with address and undefined-behaviour sanitizers.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <string>
+
+#include "../../include/lbe_csf.h"
+
+namespace lbe {
+
+constexpr int kNumS = 25;  // planes in the storage type; the two rest planes follow
+
+// Storage of the two rest populations (g_0, then hbar_0) after the 25 planes.
+// The FP64 form keeps both in FP64.  The FP32 form keeps g_0 in FP64 and
+// hbar_0 in FP32: c sits almost entirely in g_0, and its rounding enters the
+// force through eps^2 lap c (stored in FP32, or as 30-bit fixed point, g_0
+// gave the planar Marangoni velocity errors of 14% and 0.4% against the FP64
+// path), while hbar_0 is stored as the deviation from w_0 rho cv Tr(y), which
+// FP32 holds to far below the thermal signal (largest error 6e-6 in T over
+// the test cases).
+enum : int { kRestF64 = 0, kRestF32 = 1 };
+template <typename S>
+constexpr int rest_fmt(int which) {
+  return sizeof(S) == 8 || which == 0 ? kRestF64 : kRestF32;
+}
+template <typename S>
+constexpr uint32_t rest_bytes(int which) {
+  return rest_fmt<S>(which) == kRestF64 ? 8u : 4u;
+}
+// bytes of one state of n sites, and the byte offset of rest plane `which`
+template <typename S>
+constexpr size_t state_bytes_for(size_t n) {
+  return kNumS * n * sizeof(S) + n * (rest_bytes<S>(0) + rest_bytes<S>(1));
+}
+template <typename S>
+constexpr size_t rest_base(int which, size_t n) {
+  return kNumS * n * sizeof(S) + (which ? n * rest_bytes<S>(0) : 0);
+}
+
+constexpr int kNumPartials = 7;  // mass, energy, cy, cx, mass_thr, cuy_thr, nonfinite
+
+// one diagnostic record: the step and the seven FP64 sums
+struct DiagRecord {
+  int64_t step;
+  double v[kNumPartials];
+};
+
+constexpr int kAdjTX = 64;   // adjoint tile: 64 columns x 4 rows, one site per thread
+constexpr int kAdjTY = 4;
+// stencil cotangent planes: grad c, lap c, grad T, grad p, and the Hessian of
+// c (hxx, hxy, hyy; read by the curvature form only)
+constexpr int kAdjA = 10;
+
+struct AdjLayout {
+  int64_t record_steps;   // capacity N
+  int64_t K;              // checkpoint spacing for N steps
+  int64_t nchk;           // checkpoints ceil(N / K)
+  size_t state_bytes;     // one state (aligned)
+  size_t mom_bytes;       // one moment set: c (FP64), T, p, jx, jy
+  size_t plane_bytes;     // one plane of the arithmetic type
+  size_t off_chk;         // nchk states
+  size_t off_tape;        // K states, then K moment sets
+  size_t off_lam;         // D x2 (27 planes), M x2 (3 planes), A (kAdjA planes)
+  size_t off_part;        // per-block FP64 partial sums of dJ/dsigmaT
+  size_t off_tw;          // FP64 [2][nx] dJ/dTwall accumulators
+  size_t off_out;         // FP64 scalar result
+  size_t total;
+};
+
+inline int64_t adj_segment_length(int64_t nsteps) {
+  if (nsteps <= 1) return 1;
+  int64_t K = (int64_t)std::ceil(std::sqrt((double)nsteps));
+  while (K * K < nsteps) ++K;
+  while (K > 1 && (K - 1) * (K - 1) >= nsteps) --K;
+  return K;
+}
+
+inline int adj_tiles_x(int nx) { return (nx + kAdjTX - 1) / kAdjTX; }
+inline int adj_tiles_y(int ny) { return (ny + kAdjTY - 1) / kAdjTY; }
+
+inline AdjLayout adj_layout(int nx, int ny, size_t state_bytes, size_t value_bytes,
+                            int64_t record_steps) {
+  AdjLayout A{};
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  A.record_steps = record_steps;
+  if (record_steps <= 0) return A;
+  const size_t n = (size_t)nx * ny;
+  A.state_bytes = al(state_bytes);
+  A.mom_bytes = al(n * (8 + 4 * value_bytes));
+  A.plane_bytes = al(n * value_bytes);
+  A.K = adj_segment_length(record_steps);
+  A.nchk = (record_steps + A.K - 1) / A.K;
+  size_t o = 0;
+  A.off_chk = o; o += (size_t)A.nchk * A.state_bytes;
+  A.off_tape = o; o += (size_t)A.K * (A.state_bytes + A.mom_bytes);
+  A.off_lam = o; o += (2 * 27 + 2 * 3 + kAdjA) * A.plane_bytes;
+  A.off_part = o; o += al((size_t)adj_tiles_x(nx) * adj_tiles_y(ny) * sizeof(double));
+  A.off_tw = o; o += al(2 * (size_t)nx * sizeof(double));
+  A.off_out = o; o += 256;
+  A.total = o;
+  return A;
+}
+
+namespace host {
+
+constexpr int kDiagRing = 4096;
+constexpr int kNumCUs = 256;   // compute units of an MI355X (gfx950)
+constexpr size_t kLastLevelCache = size_t(256) << 20;   // MI355X Infinity Cache
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Launch {
+  int pipe;      // row pipeline of the step kernel (see step_kernel.h)
+  int nw;        // waves per block (strip width 64 * nw)
+  int nstrips;
+  int rows;      // rows per chunk
+  int nchunks;
+  int nblocks;
+  bool stream;   // plain FP32 steps use kStream (state beyond the last-level cache)
+};
+
+// two_ahead: the step may load rows two ahead (not with two densities, whose
+// step loads one row ahead)
+inline Launch pick_launch(int nx, int ny, bool fp32, bool two_ahead) {
+  Launch L;
+  // Strip width: four waves on wide grids, two from 256 columns; a narrower
+  // grid takes one strip across its whole width with at least two waves
+  // (measured 6-20% faster than one-wave strips on 8- to 200-column grids)
+  L.nw = nx >= 2048 ? 4 : (nx >= 256 ? 2 : (nx > 128 ? 4 : 2));
+  if (const char *e = std::getenv("LBE_CSF_NW")) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4 || v == 8) L.nw = v;
+  }
+  const int bx = 64 * L.nw;
+  L.nstrips = (nx + bx - 1) / bx;
+  // Row chunks: about 2048 waves (two per SIMD) resident at once -- long
+  // chunks on large grids (fewer halo rows re-read), down to one row per
+  // block on small grids, where parallelism is the limit.  The FP32 step on a
+  // large grid loads rows two ahead (PIPE 2, which needs the registers of a
+  // two-wave occupancy) and runs best with twice as many, shorter chunks.
+  auto rows_for = [&](long long waves) {
+    const long long want = std::max(1LL, waves / ((long long)L.nw * L.nstrips));
+    return (int)std::max<long long>(1, (ny + want - 1) / want);
+  };
+  int rows = rows_for(2048);
+  L.pipe = 1;
+  if (fp32 && two_ahead && rows >= 64 && nx >= 4096 && !std::getenv("LBE_CSF_NW")) {
+    // large grids: one block of eight waves (512 columns) per CU, marching
+    // long chunks; the best shape measured on 4096^2 (20.6k MLUPS)
+    L.nw = 8;
+    L.nstrips = (nx + 511) / 512;
+    const int chunks = std::max(1, kNumCUs / L.nstrips);
+    rows = (ny + chunks - 1) / chunks;
+    L.pipe = 2;
+  } else if (fp32 && rows >= 64) {
+    rows = rows_for(4096);
+    L.pipe = 2;
+  } else if (fp32 && rows >= 4) {
+    L.pipe = 2;
+  } else if (!fp32 && rows >= 64) {
+    rows = rows_for(3072);   // measured on 4096^2: 86-row chunks beat 64 and 128
+  }
+  if (const char *e = std::getenv("LBE_CSF_PIPE")) {
+    const int v = std::atoi(e);
+    if (v == 0 || v == 1 || v == 2) L.pipe = v;
+  }
+  // two densities load rows one ahead; without the eight-wave shape above
+  // the FP32 form gets 4-wave strips with 64-row chunks on 4096^2 (measured
+  // 11.9k MLUPS, against 10.7k on eight-wave strips)
+  if (!two_ahead) L.pipe = 1;
+  if (const char *e = std::getenv("LBE_CSF_ROWS")) {
+    const int v = std::atoi(e);
+    if (v >= 1) rows = v;
+  }
+  L.rows = std::min(rows, ny);
+  L.nchunks = (ny + L.rows - 1) / L.rows;
+  L.nblocks = L.nstrips * L.nchunks;
+  L.stream = false;
+  return L;
+}
+
+// two fluid densities (rho2 > 0 and different from rho)
+inline bool two_densities(const lbe_csf_params *p) { return p->rho2 > 0.0 && p->rho2 != p->rho; }
+
+struct Layout {
+  size_t state_bytes;
+  size_t off_a, off_b, off_tw, off_part, off_ring, off_cnt, off_rec, off_pc, off_adj, total;
+  AdjLayout adj;
+};
+
+inline bool params_valid(const lbe_csf_params *p, std::string *why) {
+  auto bad = [&](const char *m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (!p) return bad("params is NULL");
+  if (p->nx < 3 || p->ny < 3) return bad("nx and ny must be >= 3");
+  // the kernels address a state through one buffer descriptor (32-bit byte
+  // offsets): 25 planes of the storage type plus two FP64 planes < 4 GiB
+  const double sb = p->precision == LBE_CSF_FP64 ? (double)state_bytes_for<double>(1)
+                                                 : (double)state_bytes_for<float>(1);
+  if ((double)p->nx * (double)p->ny * sb >= 4294967296.0)
+    return bad("grid too large: a state must stay below 4 GiB");
+  if (p->walls_y != 0 && p->walls_y != 1) return bad("walls_y must be 0 or 1");
+  if (p->precision != LBE_CSF_FP64 && p->precision != LBE_CSF_FP32_DEV)
+    return bad("unknown precision");
+  auto fin = [](double v) { return std::isfinite(v); };
+  if (!(p->rho > 0) || !(p->cv > 0) || !fin(p->rho) || !fin(p->cv)) return bad("rho and cv must be > 0");
+  for (int k = 0; k < 2; ++k) {
+    if (!(p->tau_f[k] > 0.5) || !fin(p->tau_f[k])) return bad("tau_f must be > 1/2");
+    if (!(p->tau_T[k] > 0.5) || !fin(p->tau_T[k])) return bad("tau_T must be > 1/2");
+  }
+  if (!(p->tau_g > 0.5) || !fin(p->tau_g)) return bad("tau_g must be > 1/2");
+  if (!(p->mobility > 0) || !fin(p->mobility)) return bad("mobility must be > 0");
+  if (!(p->width > 0) || !fin(p->width)) return bad("width must be > 0");
+  if (!(p->beta > 0) || !fin(p->beta)) return bad("beta must be > 0");
+  if (!fin(p->sigma0) || !fin(p->sigmaT) || !fin(p->Tref) || !fin(p->force[0]) ||
+      !fin(p->force[1]) || !fin(p->p0) || !fin(p->T_shift) || !fin(p->T_grad))
+    return bad("non-finite parameter");
+  if (p->diag_every < 0) return bad("diag_every must be >= 0");
+  if (p->csf_form != 0 && p->csf_form != 1) return bad("csf_form must be 0 or 1");
+  if (!(p->rho2 >= 0.0) || !fin(p->rho2)) return bad("rho2 must be >= 0 (0: one density)");
+  // the FP32 form's linear thermal reference T_shift + T_grad y is not
+  // periodic: a population crossing a periodic y boundary would change
+  // reference by T_grad ny instead of T_grad
+  if (p->precision == LBE_CSF_FP32_DEV && p->walls_y == 0 && p->T_grad != 0.0)
+    return bad("T_grad must be 0 with periodic y in the FP32 form");
+  return true;
+}
+
+inline Layout make_layout(const lbe_csf_params *p, int64_t record_steps) {
+  Layout L{};
+  const size_t n = (size_t)p->nx * p->ny;
+  const size_t vb = p->precision == LBE_CSF_FP64 ? 8 : 4;
+  L.state_bytes = vb == 8 ? state_bytes_for<double>(n) : state_bytes_for<float>(n);
+  const Launch la = pick_launch(p->nx, p->ny, p->precision == LBE_CSF_FP32_DEV, !two_densities(p));
+  size_t o = 0;
+  L.off_a = o; o = align_up(o + L.state_bytes);
+  L.off_b = o; o = align_up(o + L.state_bytes);
+  L.off_tw = o; o = align_up(o + 2 * (size_t)p->nx * 8);
+  L.off_part = o; o = align_up(o + (size_t)la.nblocks * kNumPartials * 8);
+  L.off_ring = o; o = align_up(o + (size_t)kDiagRing * sizeof(DiagRecord));
+  L.off_cnt = o; o = align_up(o + 4 * sizeof(int64_t));
+  L.off_rec = o; o = align_up(o + sizeof(DiagRecord));
+  L.off_pc = o; o = align_up(o + (two_densities(p) ? n * 8 : 0));   // pressure of Eq. 9
+  L.off_adj = o;
+  L.adj = adj_layout(p->nx, p->ny, L.state_bytes, vb, record_steps);
+  o = align_up(o + L.adj.total);
+  L.total = o;
+  return L;
+}
+
+}  // namespace host
+}  // namespace lbe

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "host_layout.h"
+
 namespace lbe {
 
 constexpr int kQ = 9;
@@ -33,8 +35,6 @@ enum : int {
   kStream = 128 // FP32 form, state larger than the last-level cache: stores
                 // that write whole lines bypass that cache (buf_store_stream)
 };
-
-constexpr int kNumPartials = 7;  // mass, energy, cy, cx, mass_thr, cuy_thr, nonfinite
 
 // Everything a step launch needs, passed by value.  Derived constants are
 // computed once on the host in FP64 and rounded to the kernel's arithmetic

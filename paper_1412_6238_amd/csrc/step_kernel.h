@@ -56,41 +56,13 @@
 //     G = Gamma_i(u) - w_i), so no large value is formed and then subtracted.
 #pragma once
 
+#include "host_layout.h"
 #include "lattice.h"
 
 namespace lbe {
 
-constexpr int kNumS = 25;  // planes in the storage type; the two rest planes follow
-
 // plane of distribution q (0..26 = f, g, hbar; not 9 or 18, the rest planes)
 __host__ __device__ constexpr int plane_of(int q) { return q < 9 ? q : (q < 18 ? q - 1 : q - 2); }
-
-// Storage of the two rest populations (g_0, then hbar_0) after the 25 planes.
-// The FP64 form keeps both in FP64.  The FP32 form keeps g_0 in FP64 and
-// hbar_0 in FP32: c sits almost entirely in g_0, and its rounding enters the
-// force through eps^2 lap c (stored in FP32, or as 30-bit fixed point, g_0
-// gave the planar Marangoni velocity errors of 14% and 0.4% against the FP64
-// path), while hbar_0 is stored as the deviation from w_0 rho cv Tr(y), which
-// FP32 holds to far below the thermal signal (largest error 6e-6 in T over
-// the test cases).
-enum : int { kRestF64 = 0, kRestF32 = 1 };
-template <typename S>
-__host__ __device__ constexpr int rest_fmt(int which) {
-  return sizeof(S) == 8 || which == 0 ? kRestF64 : kRestF32;
-}
-template <typename S>
-__host__ __device__ constexpr uint32_t rest_bytes(int which) {
-  return rest_fmt<S>(which) == kRestF64 ? 8u : 4u;
-}
-// bytes of one state of n sites, and the byte offset of rest plane `which`
-template <typename S>
-__host__ __device__ constexpr size_t state_bytes_for(size_t n) {
-  return kNumS * n * sizeof(S) + n * (rest_bytes<S>(0) + rest_bytes<S>(1));
-}
-template <typename S>
-__host__ __device__ constexpr size_t rest_base(int which, size_t n) {
-  return kNumS * n * sizeof(S) + (which ? n * rest_bytes<S>(0) : 0);
-}
 
 // A rest population as stored (raw), and its value.  Rows loaded ahead keep
 // the raw word in registers: converting at the load would make the wave wait

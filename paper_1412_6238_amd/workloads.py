@@ -274,7 +274,8 @@ def make(name: str, **overrides) -> dict:
 
 
 # ---- the paper's own test cases at their printed parameters (Sec. IV) --------
-def paper_case(name: str, lam_r: float = 1.0, h_r: float = 1.0, **overrides) -> dict:
+def paper_case(name: str, lam_r: float = 1.0, h_r: float = 1.0, R: float = 20.0,
+               height: float = 2.0, **overrides) -> dict:
     """Sec. IV as printed: "e1" layered Poiseuille flow (40 x 100, eta_r = 10,
     lam_r in {1, 10, 100}, h_r = h/H in {1, 1/9, 9}), "e2" two superimposed
     planar fluids (200 x 100, lam_r = lam1/lam2 in {1, 0.1}, fluid 1 upper),
@@ -291,7 +292,15 @@ def paper_case(name: str, lam_r: float = 1.0, h_r: float = 1.0, **overrides) -> 
     sigma_fe / R the chemical potential of a droplet of radius R with the
     free-energy tension sigma_fe = eps^2 / (3 W) of the double well.  Below
     a critical radius, which R = 20 in 160 x 300 is, a droplet in a pure
-    matrix dissolves into it; the saturated matrix keeps it in equilibrium."""
+    matrix dissolves into it; the saturated matrix keeps it in equilibrium.
+
+    e3 also takes R (default 20) and height (the droplet centre above the
+    bottom wall in radii, default 2): a resolution series of the same
+    droplet at fixed Re = U R / nu, Ma = U R / kappa, Ca = U eta / sigma0 and
+    Cahn-Hilliard Peclet number U R / M, with the interface width W fixed
+    (so the Cahn number W / R falls as 1 / R).  With s = R / 20 the box is
+    8R x 15R, |grad T| = 0.1, sigmaT = 5e-5 / s^2, sigma0 = 0.1 / s, nu,
+    kappa and M unchanged; U = 1e-3 / s, t_r = R / U = 2e4 s^2."""
     W = W_DEFAULT
     if name == "e1":
         nx, ny = 40, 100
@@ -342,17 +351,20 @@ def paper_case(name: str, lam_r: float = 1.0, h_r: float = 1.0, **overrides) -> 
         meta = dict(h=50.0, H=50.0, eta1=0.2, eta2=0.2, lam1=lam1, lam2=lam2, Tc=10.0,
                     Th=20.0, Tr=4.0, sigma_T=-5e-4)
     elif name == "e3":
-        nx, ny = 160, 300
+        sc = R / 20.0
+        nx, ny = int(round(8 * R)), int(round(15 * R))   # 160 x 300 at R = 20
         p = base_params(nx, ny, tau_f=(0.8, 0.8), tau_T=(0.8, 0.8), tau_g=1.0, mobility=5e-2,
-                        width=W, sigma0=0.1, sigmaT=5e-5, Tref=0.0, T_shift=0.0, T_grad=0.1)
+                        width=W, sigma0=0.1 / sc, sigmaT=5e-5 / sc ** 2, Tref=0.0,
+                        T_shift=0.0, T_grad=0.1)
         eps = W * math.sqrt(0.25 / 2.0)
-        sat = (eps * eps / (3.0 * W)) / 20.0 / (2.0 * 0.25)
-        phi0 = droplet_phi(nx, ny, [(80.0, 40.0, 20.0)], W) + 2.0 * sat
+        sat = (eps * eps / (3.0 * W)) / R / (2.0 * 0.25)
+        phi0 = droplet_phi(nx, ny, [(nx / 2.0, height * R, R)], W) + 2.0 * sat
         Y, _ = coords(nx, ny)
         T0 = 0.1 * Y
-        tb, tt = np.zeros(nx), np.full(nx, 30.0)
-        nsteps = 200000                                 # 10 t_r, t_r = R / U = 2e4
-        meta = dict(R=20.0, U=1e-3, U_YGB=1.0 / 7500.0, t_r=20000)
+        tb, tt = np.zeros(nx), np.full(nx, 0.1 * ny)
+        t_r = int(round(20000 * sc * sc))               # t_r = R / U
+        nsteps = 10 * t_r
+        meta = dict(R=R, U=1e-3 / sc, U_YGB=1.0 / 7500.0 / sc, t_r=t_r)
     else:
         raise KeyError(name)
     p.update(overrides)

@@ -1,0 +1,167 @@
+// CPU driver for the library's host-side logic (host_layout.h), built with
+// AddressSanitizer and UndefinedBehaviorSanitizer by tests/test_sanitizers.py.
+// It sweeps grid shapes, precisions, walls, densities, record lengths and the
+// launch-shape overrides, and checks that every launch covers its grid, that
+// the workspace regions are aligned, ordered and large enough, that the
+// checkpoint spacing is ceil(sqrt(N)), and that invalid parameters are
+// refused with a reason.  Prints "ok <cases>" and exits 0 when all hold.
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+#include <vector>
+
+#include "host_layout.h"
+
+using namespace lbe;
+using namespace lbe::host;
+
+static int g_fail = 0;
+#define CHECK(cond, ...)                                                     \
+  do {                                                                       \
+    if (!(cond)) {                                                           \
+      std::fprintf(stderr, "FAIL %s:%d %s: ", __FILE__, __LINE__, #cond);    \
+      std::fprintf(stderr, __VA_ARGS__);                                     \
+      std::fprintf(stderr, "\n");                                            \
+      if (++g_fail > 20) std::exit(1);                                       \
+    }                                                                        \
+  } while (0)
+
+static lbe_csf_params base(int nx, int ny) {
+  lbe_csf_params p{};
+  p.nx = nx;
+  p.ny = ny;
+  p.walls_y = 1;
+  p.precision = LBE_CSF_FP32_DEV;
+  p.rho = p.cv = 1.0;
+  p.tau_f[0] = p.tau_f[1] = 0.8;
+  p.tau_T[0] = p.tau_T[1] = 0.7;
+  p.tau_g = 1.0;
+  p.mobility = 0.05;
+  p.width = 2.8284271247461903;
+  p.beta = 0.25;
+  p.sigma0 = 1e-2;
+  p.sigmaT = 5e-4;
+  p.T_grad = 0.01;
+  return p;
+}
+
+static void check_launch(const Launch &L, int nx, int ny, bool two) {
+  CHECK(L.nw == 1 || L.nw == 2 || L.nw == 4 || L.nw == 8, "nw %d", L.nw);
+  const long bx = 64L * L.nw;
+  CHECK(L.nstrips * bx >= nx && (L.nstrips - 1) * bx < nx, "strips %d x %ld for nx %d",
+        L.nstrips, bx, nx);
+  CHECK(L.rows >= 1 && L.rows <= ny, "rows %d ny %d", L.rows, ny);
+  CHECK((long)L.nchunks * L.rows >= ny && (long)(L.nchunks - 1) * L.rows < ny,
+        "chunks %d x %d for ny %d", L.nchunks, L.rows, ny);
+  CHECK(L.nblocks == L.nstrips * L.nchunks, "nblocks %d", L.nblocks);
+  CHECK(L.pipe >= 0 && L.pipe <= 2, "pipe %d", L.pipe);
+  if (two) CHECK(L.pipe == 1, "two densities need rows one ahead (pipe %d)", L.pipe);
+}
+
+static void check_layout(const lbe_csf_params &p, int64_t rec) {
+  const Layout L = make_layout(&p, rec);
+  const size_t n = (size_t)p.nx * p.ny;
+  const bool f64 = p.precision == LBE_CSF_FP64;
+  const size_t sb = f64 ? state_bytes_for<double>(n) : state_bytes_for<float>(n);
+  CHECK(L.state_bytes == sb, "state bytes");
+  const Launch la = pick_launch(p.nx, p.ny, !f64, !two_densities(&p));
+  check_launch(la, p.nx, p.ny, two_densities(&p));
+  const size_t offs[] = {L.off_a, L.off_b, L.off_tw, L.off_part, L.off_ring,
+                         L.off_cnt, L.off_rec, L.off_pc, L.off_adj};
+  for (size_t o : offs) CHECK(o % kAlign == 0, "offset %zu not aligned", o);
+  CHECK(L.off_b >= L.off_a + sb && L.off_tw >= L.off_b + sb, "states overlap");
+  CHECK(L.off_part >= L.off_tw + 2 * (size_t)p.nx * 8, "wall region");
+  CHECK(L.off_ring >= L.off_part + (size_t)la.nblocks * kNumPartials * 8, "partials region");
+  CHECK(L.off_cnt >= L.off_ring + (size_t)kDiagRing * sizeof(DiagRecord), "ring region");
+  CHECK(L.off_rec >= L.off_cnt + 4 * sizeof(int64_t), "counters");
+  CHECK(L.off_pc >= L.off_rec + sizeof(DiagRecord), "record");
+  CHECK(L.off_adj >= L.off_pc + (two_densities(&p) ? n * 8 : 0), "pressure plane");
+  CHECK(L.total >= L.off_adj + L.adj.total, "total");
+  if (rec > 0) {
+    const AdjLayout &A = L.adj;
+    CHECK(A.K * A.K >= rec && (rec <= 1 || (A.K - 1) * (A.K - 1) < rec), "K %lld for N %lld",
+          (long long)A.K, (long long)rec);
+    CHECK(A.nchk * A.K >= rec && (A.nchk - 1) * A.K < rec, "checkpoints");
+    CHECK(A.state_bytes >= sb && A.state_bytes % 256 == 0, "checkpoint state size");
+    CHECK(A.off_tape >= A.off_chk + (size_t)A.nchk * A.state_bytes, "checkpoint region");
+    CHECK(A.off_lam >= A.off_tape + (size_t)A.K * (A.state_bytes + A.mom_bytes), "tape");
+    CHECK(A.off_part >= A.off_lam + (2 * 27 + 2 * 3 + kAdjA) * A.plane_bytes, "cotangents");
+    CHECK(A.off_tw >= A.off_part + (size_t)adj_tiles_x(p.nx) * adj_tiles_y(p.ny) * 8, "adj part");
+    CHECK(A.total >= A.off_tw + 2 * (size_t)p.nx * 8 + 8, "adj total");
+  } else {
+    CHECK(L.adj.total == 0, "no adjoint region without a record");
+  }
+}
+
+int main() {
+  const int sizes[] = {3, 4, 5, 7, 8, 9, 63, 64, 65, 100, 127, 128, 129, 255, 256, 257,
+                       511, 512, 513, 1000, 2047, 2048, 4095, 4096, 5000, 8192};
+  const int64_t recs[] = {0, 1, 2, 7, 64, 4000};
+  long cases = 0;
+  for (const char *nw : {"", "1", "2", "4", "8"})
+    for (const char *rows : {"", "1", "3", "64"})
+      for (const char *pipe : {"", "0", "2"}) {
+        if (*nw) setenv("LBE_CSF_NW", nw, 1); else unsetenv("LBE_CSF_NW");
+        if (*rows) setenv("LBE_CSF_ROWS", rows, 1); else unsetenv("LBE_CSF_ROWS");
+        if (*pipe) setenv("LBE_CSF_PIPE", pipe, 1); else unsetenv("LBE_CSF_PIPE");
+        for (int nx : sizes)
+          for (int ny : sizes)
+            for (int prec : {LBE_CSF_FP64, LBE_CSF_FP32_DEV})
+              for (double rho2 : {0.0, 2.0}) {
+                lbe_csf_params p = base(nx, ny);
+                p.precision = prec;
+                p.rho2 = rho2;
+                std::string why;
+                const bool ok = params_valid(&p, &why);
+                const size_t n = (size_t)nx * ny;
+                const double sb = prec == LBE_CSF_FP64 ? (double)state_bytes_for<double>(n)
+                                                       : (double)state_bytes_for<float>(n);
+                CHECK(ok == (sb < 4294967296.0), "%dx%d prec %d: %s", nx, ny, prec, why.c_str());
+                if (!ok) {
+                  CHECK(!why.empty(), "refusal without a reason");
+                  continue;
+                }
+                for (int64_t rec : recs) {
+                  if (rec > 0 && (size_t)n * rec > (size_t)1 << 31) continue;
+                  check_layout(p, rec);
+                  ++cases;
+                }
+              }
+      }
+  unsetenv("LBE_CSF_NW");
+  unsetenv("LBE_CSF_ROWS");
+  unsetenv("LBE_CSF_PIPE");
+  // invalid parameters are refused with a reason
+  struct Bad {
+    const char *what;
+    void (*set)(lbe_csf_params &);
+  };
+  const Bad bad[] = {
+      {"nx", [](lbe_csf_params &p) { p.nx = 2; }},
+      {"ny", [](lbe_csf_params &p) { p.ny = -5; }},
+      {"tau_f", [](lbe_csf_params &p) { p.tau_f[1] = 0.5; }},
+      {"tau_T", [](lbe_csf_params &p) { p.tau_T[0] = 0.3; }},
+      {"tau_g", [](lbe_csf_params &p) { p.tau_g = 0.5; }},
+      {"mobility", [](lbe_csf_params &p) { p.mobility = 0.0; }},
+      {"width", [](lbe_csf_params &p) { p.width = -1.0; }},
+      {"beta", [](lbe_csf_params &p) { p.beta = 0.0; }},
+      {"rho", [](lbe_csf_params &p) { p.rho = 0.0; }},
+      {"walls", [](lbe_csf_params &p) { p.walls_y = 2; }},
+      {"precision", [](lbe_csf_params &p) { p.precision = 7; }},
+      {"csf_form", [](lbe_csf_params &p) { p.csf_form = 3; }},
+      {"rho2", [](lbe_csf_params &p) { p.rho2 = -1.0; }},
+      {"sigmaT", [](lbe_csf_params &p) { p.sigmaT = std::nan(""); }},
+      {"T_grad periodic", [](lbe_csf_params &p) { p.walls_y = 0; }},
+      {"diag_every", [](lbe_csf_params &p) { p.diag_every = -1; }},
+  };
+  for (const Bad &b : bad) {
+    lbe_csf_params p = base(64, 64);
+    b.set(p);
+    std::string why;
+    CHECK(!params_valid(&p, &why) && !why.empty(), "%s accepted", b.what);
+  }
+  CHECK(!params_valid(nullptr, nullptr), "NULL params accepted");
+  if (g_fail) return 1;
+  std::printf("ok %ld\n", cases);
+  return 0;
+}

@@ -181,12 +181,12 @@ def test_e2_potential_form_converges_with_mobility(lbe):
 
 
 # ---- E3 -------------------------------------------------------------------------
-def _migration(lbe, w, nsteps=200000, every=50):
-    """u_r / U_YGB averaged over each t_r = 20000 steps (the printed formula,
-    sites with c >= 1/2), and the displacement of the thresholded droplet
-    centroid per t_r in units of U_YGB."""
+def _migration(lbe, w, nsteps=200000, every=50, precision="fp64"):
+    """u_r / U_YGB averaged over each t_r (20000 steps at R = 20; the printed
+    formula, sites with c >= 1/2), and the displacement of the thresholded
+    droplet centroid per t_r in units of U_YGB."""
     m = w["meta"]
-    sim = _sim(lbe, w, diag_every=every)
+    sim = _sim(lbe, w, precision=precision, diag_every=every)
 
     def cen():
         f = _fields(sim)
@@ -259,6 +259,32 @@ def test_e3_curvature_form_at_printed_mobility(lbe):
     win, vc = _migration(lbe, w, nsteps=60000)
     _say("  u_r/U_YGB per t_r " + " ".join(f"{v:.3f}" for v in win) + f"  centroid {vc:.3f}")
     assert max(win) < 0 and vc < 0
+
+
+def test_e3_resolution_trend(lbe):
+    """The droplet of Sec. IV C refined at fixed Re, Ma, Ca and Cahn-Hilliard
+    Peclet number with the interface width fixed (R = 20 and 40, so the
+    Cahn number W / R halves), 4R above the bottom wall, both capillary
+    forms, in the FP32 form.  u_r / U_YGB rises with R in both forms and the
+    gap between the forms closes: the printed geometry is far from the
+    sharp-interface limit, which both forms approach from below (at R = 80:
+    0.49 potential, 0.18 curvature; R = 20: 0.14 and -1.27)."""
+    res = {}
+    for R in (20.0, 40.0):
+        for form in (0, 1):
+            w = wl.paper_case("e3", R=R, height=4.0, csf_form=form)
+            t_r = w["meta"]["t_r"]
+            _say(f"case E3 R={R:.0f} form={form}, 3 t_r = {3 * t_r} steps, fp32_dev")
+            win, vc = _migration(lbe, w, nsteps=3 * t_r, every=max(1, t_r // 400),
+                                 precision="fp32_dev")
+            res[(R, form)] = float(np.mean(win[1:]))
+            _say("  u_r/U_YGB per t_r " + " ".join(f"{v:.3f}" for v in win) +
+                 f"  mean(t_r 2-3) {res[(R, form)]:.3f}  thresholded centroid {vc:.3f}")
+    assert res[(40.0, 0)] > res[(20.0, 0)] + 0.1
+    assert res[(40.0, 1)] > res[(20.0, 1)] + 0.4
+    gap20 = abs(res[(20.0, 0)] - res[(20.0, 1)])
+    gap40 = abs(res[(40.0, 0)] - res[(40.0, 1)])
+    assert gap40 < 0.75 * gap20
 
 
 @pytest.mark.parametrize("name,kw", [("e1", dict(lam_r=10, h_r=1.0)), ("e2", dict(lam_r=1.0)),

@@ -13,8 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbe_csf.so")
 SOURCES = [os.path.join(CSRC, "lbe_csf.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("lattice.h", "step_kernel.h", "aux_kernels.h",
-                                           "adjoint.h")]
+HEADERS = [os.path.join(CSRC, f) for f in ("host_layout.h", "lattice.h", "step_kernel.h",
+                                           "aux_kernels.h", "adjoint.h")]
 HEADERS.append(os.path.join(ROOT, "include", "lbe_csf.h"))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -259,5 +259,39 @@ inline Layout make_layout(const lbe_csf_params *p, int64_t record_steps) {
   return L;
 }
 
+// The launch of a handle: pick_launch, and the store policy -- the FP32
+// one-density step streams whole-line stores past the last-level cache when
+// one step's source and destination states do not fit in it
+// (LBE_CSF_STREAM=0/1 forces it off/on for that step).
+inline Launch launch_for(const lbe_csf_params *p, size_t state_bytes) {
+  const bool fp32 = p->precision == LBE_CSF_FP32_DEV;
+  Launch la = pick_launch(p->nx, p->ny, fp32, !two_densities(p));
+  la.stream = fp32 && !two_densities(p) && 2 * state_bytes > kLastLevelCache;
+  if (const char *e = std::getenv("LBE_CSF_STREAM")) {
+    const int v = std::atoi(e);
+    if (v == 0 || v == 1) la.stream = v == 1 && fp32 && !two_densities(p);
+  }
+  return la;
+}
+
+// Small grids: LDS bytes of the moments c (FP64), T and p of the whole grid
+// with a halo column on each side and a row beyond each y boundary, when
+// plain steps run many per launch of one block (small_step_kernel); 0 when
+// the grid is not small enough or has two densities.  LBE_CSF_SMALL=0 turns
+// the path off.  The limit is one site per lane of a 1024-lane block:
+// measured on MI355X, 8 x 64 runs 6.0 -> 5.0 us per step (FP32) and 7.2 ->
+// 6.5 (FP64) this way, while 40 x 100 (four sites per lane) runs 5.7 -> 26
+// us: one block's CU then serialises the arithmetic that one launch per
+// step spreads over a hundred blocks.
+constexpr size_t kSmallMaxSites = 1024;
+inline size_t small_lds_bytes(const lbe_csf_params *p) {
+  if (const char *e = std::getenv("LBE_CSF_SMALL"))
+    if (std::atoi(e) == 0) return 0;
+  const size_t n = (size_t)p->nx * p->ny;
+  if (two_densities(p) || n > kSmallMaxSites) return 0;
+  const size_t r = p->precision == LBE_CSF_FP64 ? 8 : 4;
+  return (size_t)(p->nx + 2) * (p->ny + 2) * (8 + 2 * r);
+}
+
 }  // namespace host
 }  // namespace lbe

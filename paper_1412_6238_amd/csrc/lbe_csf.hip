@@ -59,6 +59,7 @@ struct lbe_csf {
   std::string err;
   StepArgs base;      // constants filled once
   int device;         // the HIP device current at creation
+  size_t small_lds;   // > 0: plain steps run many per launch (small grids)
 };
 
 namespace {
@@ -224,6 +225,41 @@ int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
   if (!launch_any(h->P.precision == LBE_CSF_FP64, mode, h->la, a, h->stream))
     return fail(h, LBE_CSF_EINVAL, "no step kernel for mode " + std::to_string(mode));
   HIPCHK(h, hipGetLastError());
+  return LBE_CSF_OK;
+}
+
+// Plain steps of a small grid, up to kSmallRun per launch of one block
+// (small_step_kernel); the states alternate as with one launch per step.
+constexpr int64_t kSmallRun = 4096;
+template <typename S, typename R, bool DEV, int MODE>
+hipError_t small_attr(size_t lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&small_step_kernel<S, R, DEV, MODE>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+template <typename S, typename R, bool DEV, int MODE>
+void small_launch(const StepArgs &a, void *other, int steps, int threads, size_t lds,
+                  hipStream_t st) {
+  small_step_kernel<S, R, DEV, MODE><<<1, threads, lds, st>>>(a, other, steps);
+}
+
+int launch_small(lbe_csf *h, int64_t nsteps) {
+  const size_t n = (size_t)h->P.nx * h->P.ny;
+  const int threads = (int)std::min<size_t>(1024, (n + 63) / 64 * 64);
+  const bool f64 = h->P.precision == LBE_CSF_FP64, curv = h->P.csf_form == 1;
+  while (nsteps > 0) {
+    const int m = (int)std::min(nsteps, kSmallRun);
+    StepArgs a = h->base;
+    a.src = h->state[h->cur];
+    void *other = h->state[1 - h->cur];
+    if (f64 && !curv) small_launch<double, double, false, kStore>(a, other, m, threads, h->small_lds, h->stream);
+    else if (f64) small_launch<double, double, false, kStore | kCurv>(a, other, m, threads, h->small_lds, h->stream);
+    else if (!curv) small_launch<float, float, true, kStore>(a, other, m, threads, h->small_lds, h->stream);
+    else small_launch<float, float, true, kStore | kCurv>(a, other, m, threads, h->small_lds, h->stream);
+    HIPCHK(h, hipGetLastError());
+    if (m & 1) h->cur = 1 - h->cur;
+    h->step += m;
+    nsteps -= m;
+  }
   return LBE_CSF_OK;
 }
 
@@ -429,19 +465,29 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   if (!h) return fail(nullptr, LBE_CSF_ENOMEM, "host allocation failed");
   h->P = *params;
   h->L = L;
-  h->la = pick_launch(params->nx, params->ny, params->precision == LBE_CSF_FP32_DEV,
-                      !two_densities(params));
-  // the FP32 one-density step streams whole-line stores past the last-level
-  // cache when one step's source and destination states do not fit in it
-  h->la.stream = params->precision == LBE_CSF_FP32_DEV && !two_densities(params) &&
-                 2 * L.state_bytes > kLastLevelCache;
-  if (const char *e = std::getenv("LBE_CSF_STREAM")) {
-    const int v = std::atoi(e);
-    if (v == 0 || v == 1)
-      h->la.stream = v == 1 && params->precision == LBE_CSF_FP32_DEV && !two_densities(params);
-  }
+  h->la = launch_for(params, L.state_bytes);
+  h->small_lds = 0;
   h->stream = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  {
+    // small grids: many plain steps per launch when the moments of the
+    // whole grid fit in one block's LDS
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) !=
+        hipSuccess)
+      max_lds = 0;
+    const size_t lds = small_lds_bytes(params);
+    if (lds > 0 && lds <= (size_t)max_lds) {
+      const bool f64 = params->precision == LBE_CSF_FP64;
+      hipError_t e = f64 ? small_attr<double, double, false, kStore>(lds)
+                         : small_attr<float, float, true, kStore>(lds);
+      if (e == hipSuccess)
+        e = f64 ? small_attr<double, double, false, kStore | kCurv>(lds)
+                : small_attr<float, float, true, kStore | kCurv>(lds);
+      if (e == hipSuccess) h->small_lds = lds;
+      (void)hipGetLastError();
+    }
+  }
   h->ws = static_cast<char *>(workspace);
   h->state[0] = h->ws + L.off_a;
   h->state[1] = h->ws + L.off_b;
@@ -517,6 +563,17 @@ int lbe_csf_step(lbe_csf *h, int64_t nsteps, int32_t record) {
   const int de = h->P.diag_every;
   bool any_diag = false;
   for (int64_t s = 0; s < nsteps; ++s) {
+    if (!record && h->small_lds > 0) {
+      // the plain steps up to the next diagnostic step, many per launch
+      int64_t run = nsteps - s;
+      if (de > 0) run = std::min<int64_t>(run, (de - h->step % de) % de);
+      if (run > 0) {
+        const int rc = launch_small(h, run);
+        if (rc != LBE_CSF_OK) return rc;
+        s += run - 1;
+        continue;
+      }
+    }
     if (record && s % K == 0) {
       // checkpoint F_{start + s}
       const int rc = adj_save_checkpoint(h->ws + h->L.off_adj, h->L.adj, s / K,

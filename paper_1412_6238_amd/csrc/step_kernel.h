@@ -717,4 +717,110 @@ step_kernel(const StepArgs a) {
   static_assert(!VR || PIPE == 1, "two densities: rows loaded one ahead");
 }
 
+// ---------------------------------------------------------------------------
+// Small grids: many steps in one launch of one block.  A grid of a few
+// thousand sites gives the per-step launch of step_kernel only a few
+// hundred waves, and its step time is the latency of one pass (loads, LDS
+// ring, collision, stores) plus the launch.  Here one block keeps the
+// moments c, T, p of the whole grid in LDS (with a column of halo on each
+// side and a ghost row beyond each wall), so a step is: every lane forms
+// the moments of its sites, a barrier, every lane collides and pushes its
+// sites into the other state (through L2: the two states of such a grid
+// stay in cache), a barrier.  The site arithmetic is site_moments and
+// site_update of the per-step kernel, and the halo and ghost values are
+// formed exactly as its ring does, so the states are bitwise the same.
+// One density; no diagnostics, fields or tape (the host runs the steps that
+// need them through step_kernel).  All waves of a block share one CU and its
+// L1, so the block barrier also orders the global stores of one step before
+// the loads of the next.
+template <typename S, typename R, bool DEV, int MODE>
+__global__ void __launch_bounds__(1024)
+small_step_kernel(const StepArgs a0, void *other, int nsteps) {
+  static_assert((MODE & (kDiag | kFields | kTape | kVarRho | kPress | kStream)) == 0,
+                "small grids: plain steps only");
+  extern __shared__ double smem[];
+  const int nx = a0.nx, ny = a0.ny;
+  const int W = nx + 2;                  // padded row: halo column on each side
+  const int H = ny + 2;                  // ghost row beyond each wall (or wrap)
+  double *lc = smem;                     // [H][W] c
+  R *lt = reinterpret_cast<R *>(lc + (size_t)H * W);   // [H][W] T (or Delta T)
+  R *lp = lt + (size_t)H * W;                          // [H][W] p (or Delta p)
+  const bool walls = a0.walls_y != 0;
+  const size_t n = (size_t)nx * (size_t)ny;
+  const Consts<R> k(a0);
+  const double inv_rcv = 1.0 / a0.rcv;
+  const uint32_t pbytes = (uint32_t)(n * sizeof(S));
+  const uint32_t rb0 = (uint32_t)rest_base<S>(0, n), rb1 = (uint32_t)rest_base<S>(1, n);
+  const int nthr = blockDim.x;
+  StepArgs a = a0;
+  const void *srcp = a0.src;
+  void *dstp = other;
+  for (int step = 0; step < nsteps; ++step) {
+    const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(srcp, state_bytes_for<S>(n));
+    auto load_site = [&](uint32_t s, RowVals<R> &r) {
+#pragma unroll
+      for (int q = 0; q < 27; ++q)
+        if (q != 9 && q != 18)
+          r.v[q] = R(buf_load<S>(rsrc, s * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes));
+      r.g0r = rest_load_raw<S, 0>(rsrc, s, rb0);
+      r.h0r = rest_load_raw<S, 1>(rsrc, s, rb1);
+    };
+    // moments of every site, with the halo columns and the ghost rows
+    for (int s = threadIdx.x; s < (int)n; s += nthr) {
+      const int x = s % nx, y = s / nx;
+      RowVals<R> r;
+      load_site((uint32_t)s, r);
+      double c, T;
+      R p;
+      site_moments<R, false>(r, inv_rcv, &c, &T, &p);
+      const R Tr = R(T);
+      // this site's cell and its copies: the halo column across the x
+      // wrap-around, and the row beyond a wall (a ghost) or across the
+      // periodic y boundary
+      const int rows[2] = {y + 1, y == 0 ? (walls ? 0 : ny + 1)
+                                         : (y == ny - 1 ? (walls ? ny + 1 : 0) : -1)};
+      const int cols[2] = {x + 1, x == 0 ? nx + 1 : (x == nx - 1 ? 0 : -1)};
+      for (int iy = 0; iy < 2; ++iy) {
+        if (rows[iy] < 0) continue;
+        const bool ghost = iy == 1 && walls;
+        for (int ix = 0; ix < 2; ++ix) {
+          if (cols[ix] < 0) continue;
+          const size_t cell = (size_t)rows[iy] * W + cols[ix];
+          lc[cell] = c;
+          lp[cell] = p;
+          if (!ghost) {
+            lt[cell] = Tr;
+          } else {
+            // beyond a wall: c and p mirrored, T_ghost = 2 T_wall - T with
+            // the wall temperature of the cell's column (deviations against
+            // the reference at the wall)
+            const bool bot = rows[iy] == 0;
+            const double *tw = bot ? a.twb : a.twt;
+            const double twref = DEV ? a.Ts + (bot ? 0.0 : a.Tg * double(ny)) : 0.0;
+            const int wc = cols[ix] == 0 ? nx - 1 : (cols[ix] == nx + 1 ? 0 : cols[ix] - 1);
+            const R twv = DEV ? R(tw[wc] - twref) : R(tw[wc]);
+            lt[cell] = R(2) * twv - Tr;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    a.src = srcp;
+    a.dst = dstp;
+    double acc[kNumPartials];
+    for (int s = threadIdx.x; s < (int)n; s += nthr) {
+      const int x = s % nx, y = s / nx;
+      RowVals<R> cur;
+      load_site((uint32_t)s, cur);
+      const size_t rS = (size_t)y * W + x, rC = rS + W, rN = rC + W;
+      site_update<S, R, DEV, MODE>(a, k, y, x, lc + rS, lc + rC, lc + rN, lt + rS, lt + rC,
+                                   lt + rN, lp + rS, lp + rC, lp + rN, cur, acc);
+    }
+    __syncthreads();
+    const void *t = srcp;
+    srcp = dstp;
+    dstp = const_cast<void *>(t);
+  }
+}
+
 }  // namespace lbe

@@ -66,6 +66,16 @@ static void check_layout(const lbe_csf_params &p, int64_t rec) {
   CHECK(L.state_bytes == sb, "state bytes");
   const Launch la = pick_launch(p.nx, p.ny, !f64, !two_densities(&p));
   check_launch(la, p.nx, p.ny, two_densities(&p));
+  // the store policy: whole-line stores bypass the last-level cache for the
+  // FP32 one-density step whose two states exceed it
+  const Launch lf = launch_for(&p, L.state_bytes);
+  CHECK(lf.nblocks == la.nblocks && lf.pipe == la.pipe, "launch_for shape");
+  CHECK(lf.stream == (!f64 && !two_densities(&p) && 2 * sb > kLastLevelCache), "store policy");
+  // the small-grid path: only one density, at most one site per lane of a
+  // 1024-lane block, and the LDS of the padded moment grid
+  const size_t sl = small_lds_bytes(&p);
+  if (two_densities(&p) || n > kSmallMaxSites) CHECK(sl == 0, "small path on %dx%d", p.nx, p.ny);
+  else CHECK(sl == (size_t)(p.nx + 2) * (p.ny + 2) * (f64 ? 24 : 16), "small LDS bytes");
   const size_t offs[] = {L.off_a, L.off_b, L.off_tw, L.off_part, L.off_ring,
                          L.off_cnt, L.off_rec, L.off_pc, L.off_adj};
   for (size_t o : offs) CHECK(o % kAlign == 0, "offset %zu not aligned", o);

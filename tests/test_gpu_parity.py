@@ -218,6 +218,33 @@ def test_fp32_store_policy_does_not_matter(lbe, monkeypatch, extra):
     np.testing.assert_array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("name,nx,ny,walls,extra", [
+    ("poiseuille", 8, 64, 1, {}), ("random", 37, 21, 0, {"csf_form": 1}),
+    ("random", 30, 34, 1, {}), ("random", 3, 5, 0, {})])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
+def test_small_grid_path_matches_per_step(lbe, monkeypatch, name, nx, ny, walls, extra,
+                                          precision):
+    """Small grids run their plain steps many per launch of one block
+    (small_step_kernel, the moments of the whole grid in LDS); the states are
+    bitwise those of one launch per step, with diagnostics every 7 steps
+    interleaved and an odd number of steps."""
+    if name == "poiseuille":
+        w = wl.make("poiseuille")
+    else:
+        w = wl.random_case(nx, ny, seed=nx + ny, walls_y=walls, **extra)
+    out = []
+    for small in ("0", "1"):
+        monkeypatch.setenv("LBE_CSF_SMALL", small)
+        _say(f"case small-grid path={small} {name} {nx}x{ny} {precision} {extra}")
+        sim = lbe.Simulation(dict(w["params"], **extra), w["phi0"], w["T0"], w["Twall_bot"],
+                             w["Twall_top"], precision=precision, diag_every=7)
+        sim.step(53)
+        sim.step(4)
+        out.append((sim.get_state().cpu().numpy(), sim.diag_history(), sim.step_count))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2] == 57
+
+
 def test_fp64_chunking_does_not_matter(lbe, oracle_mod, monkeypatch):
     """Different strip widths and chunk heights give bitwise-identical states."""
     case = wl.random_case(200, 60, seed=12, walls_y=1)

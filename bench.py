@@ -31,9 +31,9 @@ BYTES_PER_SITE = {"fp32_dev": 216, "fp64": 432}
 # the rest population g_0 in FP64, 2 x (26 x 4 + 8) = 224
 STORED_BYTES_PER_SITE = {"fp32_dev": 224, "fp64": 432}
 REPEATS = 5
-# the step kernel and its launch shape (chosen in lbe_csf.hip)
+# the step kernel and its launch shape and store policy (host_layout.h)
 KERNEL_SOURCES = ("paper_1412_6238_amd/csrc/step_kernel.h", "paper_1412_6238_amd/csrc/lattice.h",
-                  "paper_1412_6238_amd/csrc/lbe_csf.hip")
+                  "paper_1412_6238_amd/csrc/host_layout.h")
 
 
 def kernel_hash():

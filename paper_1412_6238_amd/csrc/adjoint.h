@@ -368,12 +368,15 @@ adj_collide_kernel(const AdjArgs aa) {
     if (VARTAU) {
       const __amdgpu_buffer_rsrc_t rs =
           plane_rsrc(a.src, state_bytes_for<R>(n));
+      const uint32_t ro = (uint32_t)y * (uint32_t)row_bytes<R>(nx);
+      const uint32_t segb = (uint32_t)(nx * sizeof(R));   // a plane's segment of a row
 #pragma unroll
       for (int q = 0; q < 27; ++q)
         if (q != 9 && q != 18)
-          cur.v[q] = buf_load<R>(rs, s * (uint32_t)sizeof(R), (uint32_t)plane_of(q) * pb);
-      cur.g0r = rest_load_raw<R, 0>(rs, s, (uint32_t)rest_base<R>(0, n));
-      cur.h0r = rest_load_raw<R, 1>(rs, s, (uint32_t)rest_base<R>(1, n));
+          cur.v[q] = buf_load<R>(rs, ro + (uint32_t)x * (uint32_t)sizeof(R),
+                                 (uint32_t)plane_of(q) * segb);
+      cur.g0r = rest_load_raw<R, 0>(rs, ro, x, (uint32_t)rest_base<R>(0, nx));
+      cur.h0r = rest_load_raw<R, 1>(rs, ro, x, (uint32_t)rest_base<R>(1, nx));
     }
     constexpr int NA = CURV ? kAdjA : 7;
     R db[27], da[kAdjA];

@@ -11,7 +11,8 @@ namespace lbe {
 // equilibrium (Sec. II Eqs. 7, 13-14; Sec. III Eq. 22).  FP32 form: stored as
 // deviations, so f - w p0 = 0 and hbar - w rho cv Tr = w rho cv (T0 - Tr)
 // with the linear reference Tr = Ts + Tg (y + 1/2) of the site's row.
-// Layout as in step_kernel.h: 25 planes of S, then the rest planes g_0 and hbar_0.
+// Layout as in host_layout.h: rows of 25 plane segments of S, then the rest
+// populations g_0 and hbar_0.
 template <typename S, bool DEV>
 __global__ void __launch_bounds__(256)
 init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
@@ -21,7 +22,6 @@ init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= nx || y >= ny) return;
-  const size_t n = (size_t)nx * ny;
   const size_t s = (size_t)y * nx + x;
   auto cval = [&](int dx, int dy) {
     int xx = x + dx;
@@ -49,15 +49,15 @@ init_kernel(S *__restrict__ F, const double *__restrict__ phi0,
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const double w = wq<double>(i);
-    F[plane_of(i) * n + s] = DEV ? S(0) : S(w * p0);
+    F[plane_index<S>(plane_of(i), nx, y, x)] = DEV ? S(0) : S(w * p0);
     const double hv = DEV ? (drho != 0.0 ? w * (rcv_s * T - rcv * Tr) : w * rcv * (T - Tr))
                           : w * rcv_s * T;
     if (i == 0) {
-      rest_set<S, 0>(F, n, s, c - (1.0 - w) * gmu);
-      rest_set<S, 1>(F, n, s, hv);
+      rest_set<S, 0>(F, nx, y, x, c - (1.0 - w) * gmu);
+      rest_set<S, 1>(F, nx, y, x, hv);
     } else {
-      F[plane_of(9 + i) * n + s] = S(w * gmu);
-      F[plane_of(18 + i) * n + s] = S(hv);
+      F[plane_index<S>(plane_of(9 + i), nx, y, x)] = S(w * gmu);
+      F[plane_index<S>(plane_of(18 + i), nx, y, x)] = S(hv);
     }
   }
 }
@@ -103,7 +103,7 @@ diag_reduce_kernel(const double *__restrict__ partials, int nblocks,
   }
 }
 
-// FP64 [27][n] <-> storage form (25 planes of S + the rest planes g_0, hbar_0).
+// FP64 [27][n] <-> storage form (row-interleaved, host_layout.h).
 template <typename S, bool DEV>
 __global__ void __launch_bounds__(256)
 state_to_f64(const S *__restrict__ F, double *__restrict__ out, int nx, int ny,
@@ -113,11 +113,13 @@ state_to_f64(const S *__restrict__ F, double *__restrict__ out, int nx, int ny,
   const int q = blockIdx.y;
   if (s >= n) return;
   const int i = q % 9;
-  double v = q == 9 ? rest_get<S, 0>(F, n, s)
-                    : (q == 18 ? rest_get<S, 1>(F, n, s) : double(F[plane_of(q) * n + s]));
+  const size_t y = s / nx, x = s % nx;
+  double v = q == 9 ? rest_get<S, 0>(F, nx, y, x)
+                    : (q == 18 ? rest_get<S, 1>(F, nx, y, x)
+                               : double(F[plane_index<S>(plane_of(q), nx, y, x)]));
   if (DEV) {
     if (q < 9) v += wq<double>(i) * p0;
-    else if (q >= 18) v += wq<double>(i) * rcv * (Ts + Tg * (double(s / nx) + 0.5));
+    else if (q >= 18) v += wq<double>(i) * rcv * (Ts + Tg * (double(y) + 0.5));
   }
   out[q * n + s] = v;
 }
@@ -131,14 +133,15 @@ state_from_f64(S *__restrict__ F, const double *__restrict__ in, int nx, int ny,
   const int q = blockIdx.y;
   if (s >= n) return;
   const int i = q % 9;
+  const size_t y = s / nx, x = s % nx;
   double v = in[q * n + s];
   if (DEV) {
     if (q < 9) v -= wq<double>(i) * p0;
-    else if (q >= 18) v -= wq<double>(i) * rcv * (Ts + Tg * (double(s / nx) + 0.5));
+    else if (q >= 18) v -= wq<double>(i) * rcv * (Ts + Tg * (double(y) + 0.5));
   }
-  if (q == 9) rest_set<S, 0>(F, n, s, v);
-  else if (q == 18) rest_set<S, 1>(F, n, s, v);
-  else F[plane_of(q) * n + s] = S(v);
+  if (q == 9) rest_set<S, 0>(F, nx, y, x, v);
+  else if (q == 18) rest_set<S, 1>(F, nx, y, x, v);
+  else F[plane_index<S>(plane_of(q), nx, y, x)] = S(v);
 }
 
 }  // namespace lbe

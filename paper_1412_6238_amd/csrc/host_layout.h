@@ -35,14 +35,24 @@ template <typename S>
 constexpr uint32_t rest_bytes(int which) {
   return rest_fmt<S>(which) == kRestF64 ? 8u : 4u;
 }
-// bytes of one state of n sites, and the byte offset of rest plane `which`
+// bytes of one state of n sites
 template <typename S>
 constexpr size_t state_bytes_for(size_t n) {
   return kNumS * n * sizeof(S) + n * (rest_bytes<S>(0) + rest_bytes<S>(1));
 }
+// The state is row-interleaved: row y is one record of row_bytes<S>(nx)
+// bytes that holds the row's nx values of each of the 25 storage planes in
+// turn (plane p at p * nx * sizeof(S)), then those of g_0 and of hbar_0 (at
+// rest_base<S>(0 or 1, nx)).  A row's 27 segments are thus contiguous, which
+// a row-marching step reads and writes as one stream per row instead of 27
+// streams a plane apart.
 template <typename S>
-constexpr size_t rest_base(int which, size_t n) {
-  return kNumS * n * sizeof(S) + (which ? n * rest_bytes<S>(0) : 0);
+constexpr size_t row_bytes(size_t nx) {
+  return state_bytes_for<S>(nx);
+}
+template <typename S>
+constexpr size_t rest_base(int which, size_t nx) {
+  return kNumS * nx * sizeof(S) + (which ? nx * rest_bytes<S>(0) : 0);
 }
 
 constexpr int kNumPartials = 7;  // mass, energy, cy, cx, mass_thr, cuy_thr, nonfinite

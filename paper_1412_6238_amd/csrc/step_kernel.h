@@ -74,37 +74,51 @@ __device__ __forceinline__ double rest_decode(typename RestRaw<F>::T v) {
   return double(v);
 }
 
-// rest population of a site through the state's buffer descriptor (base: the
-// plane's byte offset)
+// Addresses in the row-interleaved state (host_layout.h): the value of
+// storage plane p at (x, y) sits at byte y * row_bytes + p * nx * sizeof(S)
+// + x * sizeof(S).  Buffer accesses take the row's offset plus the lane's
+// column as the per-lane offset and the plane's offset within the row as the
+// scalar base.
+
+// rest population of a site through the state's buffer descriptor (row_off:
+// the row's byte offset, base: the rest plane's offset within a row)
 template <typename S, int W>
 __device__ __forceinline__ typename RestRaw<rest_fmt<S>(W)>::T rest_load_raw(
-    __amdgpu_buffer_rsrc_t r, uint32_t site, uint32_t base) {
+    __amdgpu_buffer_rsrc_t r, uint32_t row_off, int x, uint32_t base) {
   using T = typename RestRaw<rest_fmt<S>(W)>::T;
-  return buf_load<T>(r, site * (uint32_t)sizeof(T), base);
+  return buf_load<T>(r, row_off + (uint32_t)x * (uint32_t)sizeof(T), base);
 }
 template <typename S, int W>
-__device__ __forceinline__ double rest_load(__amdgpu_buffer_rsrc_t r, uint32_t site,
+__device__ __forceinline__ double rest_load(__amdgpu_buffer_rsrc_t r, uint32_t row_off, int x,
                                             uint32_t base) {
-  return rest_decode<rest_fmt<S>(W)>(rest_load_raw<S, W>(r, site, base));
+  return rest_decode<rest_fmt<S>(W)>(rest_load_raw<S, W>(r, row_off, x, base));
 }
 template <typename S, int W, bool STREAM>
-__device__ __forceinline__ void rest_store(double v, __amdgpu_buffer_rsrc_t r, uint32_t site,
-                                           uint32_t base) {
+__device__ __forceinline__ void rest_store(double v, __amdgpu_buffer_rsrc_t r, uint32_t row_off,
+                                           int x, uint32_t base) {
   using T = typename RestRaw<rest_fmt<S>(W)>::T;
-  if constexpr (STREAM) buf_store_stream<T>(T(v), r, site * (uint32_t)sizeof(T), base);
-  else buf_store<T>(T(v), r, site * (uint32_t)sizeof(T), base);
+  const uint32_t off = row_off + (uint32_t)x * (uint32_t)sizeof(T);
+  if constexpr (STREAM) buf_store_stream<T>(T(v), r, off, base);
+  else buf_store<T>(T(v), r, off, base);
 }
-// the same through plain pointers (set-up and conversion kernels)
+// the same through plain pointers (set-up and conversion kernels): storage
+// plane p of site (x, y) as an index into the state viewed as S[], and the
+// rest populations
+template <typename S>
+__host__ __device__ __forceinline__ size_t plane_index(int p, size_t nx, size_t y, size_t x) {
+  return y * (row_bytes<S>(nx) / sizeof(S)) + (size_t)p * nx + x;
+}
 template <typename S, int W>
-__device__ __forceinline__ double rest_get(const void *state, size_t n, size_t s) {
+__device__ __forceinline__ double rest_get(const void *state, size_t nx, size_t y, size_t x) {
   using T = typename RestRaw<rest_fmt<S>(W)>::T;
   return double(reinterpret_cast<const T *>(static_cast<const char *>(state) +
-                                            rest_base<S>(W, n))[s]);
+                                            y * row_bytes<S>(nx) + rest_base<S>(W, nx))[x]);
 }
 template <typename S, int W>
-__device__ __forceinline__ void rest_set(void *state, size_t n, size_t s, double v) {
+__device__ __forceinline__ void rest_set(void *state, size_t nx, size_t y, size_t x, double v) {
   using T = typename RestRaw<rest_fmt<S>(W)>::T;
-  reinterpret_cast<T *>(static_cast<char *>(state) + rest_base<S>(W, n))[s] = T(v);
+  reinterpret_cast<T *>(static_cast<char *>(state) + y * row_bytes<S>(nx) +
+                        rest_base<S>(W, nx))[x] = T(v);
 }
 
 // constants in the kernel's arithmetic type
@@ -284,7 +298,8 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     // one descriptor for the whole destination state (below 4 GiB); planes
     // are selected by a scalar offset
     const __amdgpu_buffer_rsrc_t rd = plane_rsrc(a.dst, state_bytes_for<S>(n));
-    const uint32_t pbytes = (uint32_t)(n * sizeof(S));
+    const uint32_t pbytes = (uint32_t)(nx * sizeof(S));   // a plane's segment of a row
+    const uint32_t RB = (uint32_t)row_bytes<S>(nx);
     const R ch = c < R(0) ? R(0) : (c > R(1) ? R(1) : c);
     const double wfd = 1.0 / (a.tauf0 + double(ch) * a.dtauf), cfd = 1.0 - 0.5 * wfd;
     const double usqd = uxd * uxd + uyd * uyd;
@@ -310,18 +325,19 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     const R src_h = R(3) * irho;              // 1 / (rho cs^2)
     const bool walls = a.walls_y != 0;
     const bool bot = walls && j == 0, top = walls && j == ny - 1;
-    const uint32_t s_own = (uint32_t)(j * nx + x);
-    auto st = [&](int q, uint32_t off, R val) {
-      buf_store<S>(S(val), rd, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes);
+    const uint32_t own = (uint32_t)j * RB;   // this row's offset
+    auto st = [&](int q, uint32_t row_off, int xs, R val) {
+      buf_store<S>(S(val), rd, row_off + (uint32_t)xs * (uint32_t)sizeof(S),
+                   (uint32_t)plane_of(q) * pbytes);
     };
     // stores whose lines this wave writes whole
     constexpr bool stream = (MODE & kStream) != 0;
-    auto st_whole = [&](int q, uint32_t off, R val) {
+    auto st_whole = [&](int q, uint32_t row_off, int xs, R val) {
+      const uint32_t off = row_off + (uint32_t)xs * (uint32_t)sizeof(S);
       if constexpr (stream)
-        buf_store_stream<S>(S(val), rd, off * (uint32_t)sizeof(S),
-                            (uint32_t)plane_of(q) * pbytes);
+        buf_store_stream<S>(S(val), rd, off, (uint32_t)plane_of(q) * pbytes);
       else
-        buf_store<S>(S(val), rd, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes);
+        buf_store<S>(S(val), rd, off, (uint32_t)plane_of(q) * pbytes);
     };
     // FP32 form: what the eight moving populations of g and hbar give away in
     // this collision, as stored (sum of old - new, each difference of two
@@ -362,7 +378,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const R heq_full = rcvT * gam;
       const R hsrc = chf * src_h * fhe * heq_full;
       if (i == 0) {
-        st_whole(0, s_own, fo);
+        st_whole(0, own, x, fo);
         gsrc0 = gsrc;
         hsrc0 = hsrc;
         G0 = G;
@@ -385,33 +401,33 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
         const int o = kOpp[i];
         const double *tw = kEy[i] < 0 ? a.twb : a.twt;
         const R twv = DEV ? R(tw[x] - Trow) : R(tw[x]);
-        st(o, s_own, fo);
-        st(9 + o, s_own, go);
+        st(o, own, x, fo);
+        st(9 + o, own, x, go);
         if constexpr (DEV && VR)
-          st(18 + o, s_own, R(2) * w * (R(rcv_s) * twv + R(hoff_d)) - ho);
+          st(18 + o, own, x, R(2) * w * (R(rcv_s) * twv + R(hoff_d)) - ho);
         else
-          st(18 + o, s_own, R(2) * w * (VR ? R(rcv_s) : k.rcv) * twv - ho);
+          st(18 + o, own, x, R(2) * w * (VR ? R(rcv_s) : k.rcv) * twv - ho);
         dh += cur.v[18 + i] - ho;
       } else {
         int xd = x + kEx[i];
         xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
         int yd = j + kEy[i];
         yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
-        const uint32_t s = (uint32_t)(yd * nx + xd);
+        const uint32_t ro = (uint32_t)yd * RB;
         if (kEx[i] == 0) {
-          st_whole(i, s, fo);
-          st_whole(9 + i, s, go);
+          st_whole(i, ro, xd, fo);
+          st_whole(9 + i, ro, xd, go);
         } else {
-          st(i, s, fo);
-          st(9 + i, s, go);
+          st(i, ro, xd, fo);
+          st(9 + i, ro, xd, go);
         }
         // a move to the next row changes the reference by Tg xi_y
         const R shift = DEV && kEy[i] != 0 ? R(kEy[i]) * w * k.rcv * R(a.Tg) : R(0);
         const R hst = ho - shift;
         if (kEx[i] == 0)
-          st_whole(18 + i, s, hst);
+          st_whole(18 + i, ro, xd, hst);
         else
-          st(18 + i, s, hst);
+          st(18 + i, ro, xd, hst);
         dh += (cur.v[18 + i] - hst) - shift;
       }
     }
@@ -434,8 +450,8 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const double hdiff = cur.h0() - rcv_s * Tfull_d * double(gam0);
       hnew = cur.h0() + double(-wT * R(hdiff) + hsrc0);
     }
-    rest_store<S, 0, stream>(gnew, rd, s_own, (uint32_t)rest_base<S>(0, n));
-    rest_store<S, 1, stream>(hnew, rd, s_own, (uint32_t)rest_base<S>(1, n));
+    rest_store<S, 0, stream>(gnew, rd, own, x, (uint32_t)rest_base<S>(0, nx));
+    rest_store<S, 1, stream>(hnew, rd, own, x, (uint32_t)rest_base<S>(1, nx));
   }
 }
 
@@ -498,11 +514,15 @@ step_kernel(const StepArgs a) {
   const double inv_rcv = 1.0 / a.rcv;
 
   // helper lanes: 0..2 sum the left halo column's c, T, p, 3..5 the right
-  // one's; with six waves or more one helper per wave (its last lane), so
-  // that no wave carries all the halo loads (measured on 4096^2: 1.1%
-  // faster than six helpers in the last wave), else lanes 0..5 of the last
-  // wave
-  const int hl = NW >= 6 ? ((lane & 63) == 63 ? (lane >> 6) : -1) : lane - (BX - 64);
+  // one's.  Eight-wave strips and the FP64 step spread them over the waves
+  // (the last ceil(6 / NW) lanes of each), so that no wave carries all the
+  // halo loads; measured on 4096^2: FP32 eight waves 1.1% faster, FP64 four
+  // waves 1.3% faster, but the FP32 four-wave step on 4096 x 1024 0.4% slower, so
+  // there lanes 0..5 of the last wave keep them
+  constexpr bool kSpread = NW >= 6 || sizeof(S) == 8;
+  constexpr int kHPW = (6 + NW - 1) / NW;   // helpers per wave
+  const int hli = 63 - (lane & 63);
+  const int hl = kSpread ? (hli < kHPW ? (lane >> 6) * kHPW + hli : -1) : lane - (BX - 64);
   const bool halo = hl >= 0 && hl < 6;
   const int hside = hl / 3;
   const int hfield = hl - 3 * hside;  // 0: c, 1: T, 2: p
@@ -512,25 +532,28 @@ step_kernel(const StepArgs a) {
   // one descriptor for the whole source state (below 4 GiB); planes are
   // selected by a scalar offset
   const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(src, state_bytes_for<S>(n));
-  const uint32_t pbytes = (uint32_t)(n * sizeof(S));
-  auto ld = [&](int q, uint32_t off) {
-    return R(buf_load<S>(rsrc, off * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes));
+  const uint32_t pbytes = (uint32_t)(nx * sizeof(S));   // a plane's segment of a row
+  const uint32_t RB = (uint32_t)row_bytes<S>(nx);
+  auto ld = [&](int q, uint32_t row_off, int xs) {
+    return R(buf_load<S>(rsrc, row_off + (uint32_t)xs * (uint32_t)sizeof(S),
+                         (uint32_t)plane_of(q) * pbytes));
   };
-  const uint32_t rb0 = (uint32_t)rest_base<S>(0, n), rb1 = (uint32_t)rest_base<S>(1, n);
-  auto ldd = [&](int which, uint32_t off) {
-    return which == 0 ? rest_load<S, 0>(rsrc, off, rb0) : rest_load<S, 1>(rsrc, off, rb1);
+  const uint32_t rb0 = (uint32_t)rest_base<S>(0, nx), rb1 = (uint32_t)rest_base<S>(1, nx);
+  auto ldd = [&](int which, uint32_t row_off, int xs) {
+    return which == 0 ? rest_load<S, 0>(rsrc, row_off, xs, rb0)
+                      : rest_load<S, 1>(rsrc, row_off, xs, rb1);
   };
   auto wrap_row = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
   auto is_ghost = [&](int row) { return walls && (row < 0 || row >= ny); };
 
   auto load_row = [&](int row, RowVals<R> &r) {
     if (act) {
-      const uint32_t s = (uint32_t)(row * nx + x);
+      const uint32_t ro = (uint32_t)row * RB;
 #pragma unroll
       for (int q = 0; q < 27; ++q)
-        if (q != 9 && q != 18) r.v[q] = ld(q, s);
-      r.g0r = rest_load_raw<S, 0>(rsrc, s, rb0);
-      r.h0r = rest_load_raw<S, 1>(rsrc, s, rb1);
+        if (q != 9 && q != 18) r.v[q] = ld(q, ro, x);
+      r.g0r = rest_load_raw<S, 0>(rsrc, ro, x, rb0);
+      r.h0r = rest_load_raw<S, 1>(rsrc, ro, x, rb1);
     }
   };
   // a helper lane's halo values: the nine planes of its field, and the FP64
@@ -542,15 +565,15 @@ step_kernel(const StepArgs a) {
   };
   auto load_halo = [&](int row, HaloVals &h) {
     if (halo) {
-      const uint32_t s = (uint32_t)(row * nx + hx);
+      const uint32_t ro = (uint32_t)row * RB;
       if (hfield == 2) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) h.v[q] = ld(q, s);
+        for (int q = 0; q < 9; ++q) h.v[q] = ld(q, ro, hx);
       } else {
 #pragma unroll
-        for (int q = 1; q < 9; ++q) h.v[q] = ld(9 * (hfield + 1) + q, s);
-        if (hfield == 0) h.g0r = rest_load_raw<S, 0>(rsrc, s, rb0);
-        else h.h0r = rest_load_raw<S, 1>(rsrc, s, rb1);
+        for (int q = 1; q < 9; ++q) h.v[q] = ld(9 * (hfield + 1) + q, ro, hx);
+        if (hfield == 0) h.g0r = rest_load_raw<S, 0>(rsrc, ro, hx, rb0);
+        else h.h0r = rest_load_raw<S, 1>(rsrc, ro, hx, rb1);
       }
     }
   };
@@ -594,32 +617,33 @@ step_kernel(const StepArgs a) {
   // halo moments loaded and summed in place (PIPE 0, 1)
   auto put_halo_direct = [&](int slot, int row) {
     if (halo) {
-      const uint32_t s = (uint32_t)(row * nx + hx);
+      const uint32_t ro = (uint32_t)row * RB;
       if (hfield == 0) {
         R cs = 0;
 #pragma unroll
-        for (int q = 1; q < 9; ++q) cs += ld(9 + q, s);
-        ringc[slot][hpos] = ldd(0, s) + double(cs);
+        for (int q = 1; q < 9; ++q) cs += ld(9 + q, ro, hx);
+        ringc[slot][hpos] = ldd(0, ro, hx) + double(cs);
       } else if (hfield == 1) {
         R hs = 0;
 #pragma unroll
-        for (int q = 1; q < 9; ++q) hs += ld(18 + q, s);
+        for (int q = 1; q < 9; ++q) hs += ld(18 + q, ro, hx);
         if (VR) {
           R cs = 0;
 #pragma unroll
-          for (int q = 1; q < 9; ++q) cs += ld(9 + q, s);
-          const double ch = ldd(0, s) + double(cs);
-          ringt[slot][hpos] = R((ldd(1, s) + double(hs) - ch * a.drho * a.cv * tref_of(row)) /
-                                ((a.rho + ch * a.drho) * a.cv));
+          for (int q = 1; q < 9; ++q) cs += ld(9 + q, ro, hx);
+          const double ch = ldd(0, ro, hx) + double(cs);
+          ringt[slot][hpos] =
+              R((ldd(1, ro, hx) + double(hs) - ch * a.drho * a.cv * tref_of(row)) /
+                ((a.rho + ch * a.drho) * a.cv));
         } else {
-          ringt[slot][hpos] = R((ldd(1, s) + double(hs)) * inv_rcv);
+          ringt[slot][hpos] = R((ldd(1, ro, hx) + double(hs)) * inv_rcv);
         }
       } else if (VRP) {
         ringp[slot][hpos] = R(a.pc[(size_t)row * nx + hx]);
       } else {
         R f = 0;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) f += ld(q, s);
+        for (int q = 0; q < 9; ++q) f += ld(q, ro, hx);
         ringp[slot][hpos] = f;
       }
     }
@@ -749,27 +773,30 @@ small_step_kernel(const StepArgs a0, void *other, int nsteps) {
   const size_t n = (size_t)nx * (size_t)ny;
   const Consts<R> k(a0);
   const double inv_rcv = 1.0 / a0.rcv;
-  const uint32_t pbytes = (uint32_t)(n * sizeof(S));
-  const uint32_t rb0 = (uint32_t)rest_base<S>(0, n), rb1 = (uint32_t)rest_base<S>(1, n);
+  const uint32_t pbytes = (uint32_t)(nx * sizeof(S));   // a plane's segment of a row
+  const uint32_t RB = (uint32_t)row_bytes<S>(nx);
+  const uint32_t rb0 = (uint32_t)rest_base<S>(0, nx), rb1 = (uint32_t)rest_base<S>(1, nx);
   const int nthr = blockDim.x;
   StepArgs a = a0;
   const void *srcp = a0.src;
   void *dstp = other;
   for (int step = 0; step < nsteps; ++step) {
     const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(srcp, state_bytes_for<S>(n));
-    auto load_site = [&](uint32_t s, RowVals<R> &r) {
+    auto load_site = [&](int y, int x, RowVals<R> &r) {
+      const uint32_t ro = (uint32_t)y * RB;
 #pragma unroll
       for (int q = 0; q < 27; ++q)
         if (q != 9 && q != 18)
-          r.v[q] = R(buf_load<S>(rsrc, s * (uint32_t)sizeof(S), (uint32_t)plane_of(q) * pbytes));
-      r.g0r = rest_load_raw<S, 0>(rsrc, s, rb0);
-      r.h0r = rest_load_raw<S, 1>(rsrc, s, rb1);
+          r.v[q] = R(buf_load<S>(rsrc, ro + (uint32_t)x * (uint32_t)sizeof(S),
+                                 (uint32_t)plane_of(q) * pbytes));
+      r.g0r = rest_load_raw<S, 0>(rsrc, ro, x, rb0);
+      r.h0r = rest_load_raw<S, 1>(rsrc, ro, x, rb1);
     };
     // moments of every site, with the halo columns and the ghost rows
     for (int s = threadIdx.x; s < (int)n; s += nthr) {
       const int x = s % nx, y = s / nx;
       RowVals<R> r;
-      load_site((uint32_t)s, r);
+      load_site(y, x, r);
       double c, T;
       R p;
       site_moments<R, false>(r, inv_rcv, &c, &T, &p);
@@ -811,7 +838,7 @@ small_step_kernel(const StepArgs a0, void *other, int nsteps) {
     for (int s = threadIdx.x; s < (int)n; s += nthr) {
       const int x = s % nx, y = s / nx;
       RowVals<R> cur;
-      load_site((uint32_t)s, cur);
+      load_site(y, x, cur);
       const size_t rS = (size_t)y * W + x, rC = rS + W, rN = rC + W;
       site_update<S, R, DEV, MODE>(a, k, y, x, lc + rS, lc + rC, lc + rN, lt + rS, lt + rC,
                                    lt + rN, lp + rS, lp + rC, lp + rN, cur, acc);

@@ -64,6 +64,17 @@ static void check_layout(const lbe_csf_params &p, int64_t rec) {
   const bool f64 = p.precision == LBE_CSF_FP64;
   const size_t sb = f64 ? state_bytes_for<double>(n) : state_bytes_for<float>(n);
   CHECK(L.state_bytes == sb, "state bytes");
+  // row-interleaved state: ny rows of row_bytes, each 25 plane segments then
+  // g_0 and hbar_0; every byte offset a kernel forms fits its 32-bit offset
+  const size_t rb = f64 ? row_bytes<double>(p.nx) : row_bytes<float>(p.nx);
+  const size_t vb = f64 ? 8 : 4;
+  CHECK(rb * p.ny == sb, "rows x row bytes");
+  const size_t r0 = f64 ? rest_base<double>(0, p.nx) : rest_base<float>(0, p.nx);
+  const size_t r1 = f64 ? rest_base<double>(1, p.nx) : rest_base<float>(1, p.nx);
+  CHECK(r0 == kNumS * p.nx * vb, "g_0 after the 25 plane segments");
+  CHECK(r1 == r0 + (size_t)p.nx * 8, "hbar_0 after g_0 (FP64)");
+  CHECK(r1 + (size_t)p.nx * vb == rb, "hbar_0 ends the row");
+  CHECK(sb - 1 <= 0xffffffffull, "state offsets fit 32 bits");
   const Launch la = pick_launch(p.nx, p.ny, !f64, !two_densities(&p));
   check_launch(la, p.nx, p.ny, two_densities(&p));
   // the store policy: whole-line stores bypass the last-level cache for the

@@ -163,14 +163,24 @@ inline Launch pick_launch(int nx, int ny, bool fp32, bool two_ahead) {
   };
   int rows = rows_for(2048);
   L.pipe = 1;
-  if (fp32 && two_ahead && rows >= 64 && nx >= 4096 && !std::getenv("LBE_CSF_NW")) {
-    // large grids: one block of eight waves (512 columns) per CU, marching
-    // long chunks; the best shape measured on 4096^2 (20.6k MLUPS)
-    L.nw = 8;
-    L.nstrips = (nx + 511) / 512;
-    const int chunks = std::max(1, kNumCUs / L.nstrips);
-    rows = (ny + chunks - 1) / chunks;
-    L.pipe = 2;
+  // One block per CU marching long chunks (one density): eight-wave strips
+  // loading rows two ahead in the FP32 step, four-wave strips loading one row
+  // ahead in FP64.  Measured on the row-interleaved state against the shapes
+  // below (interleaved timing windows after a warm-up, nine grids from
+  // 1024 x 512 to 8192 x 1024): FP32 up to 11% faster and none slower (the
+  // same on 4096^2 and 8192 x 1024, which already had this shape), FP64 2-8%
+  // faster everywhere, and within 1.5% of the best shape of a wider sweep.
+  // Taken when the chunks are at least four rows long.
+  const int nw1 = fp32 ? 8 : 4;
+  const int nstr1 = (nx + 64 * nw1 - 1) / (64 * nw1);
+  const int chunks1 = std::max(1, kNumCUs / nstr1);
+  const int rows1 = (ny + chunks1 - 1) / chunks1;
+  const bool one_per_cu = two_ahead && nx >= 64 * nw1 && rows1 >= 4;
+  if (one_per_cu && !std::getenv("LBE_CSF_NW")) {
+    L.nw = nw1;
+    L.nstrips = nstr1;
+    rows = rows1;
+    L.pipe = fp32 ? 2 : 1;
   } else if (fp32 && rows >= 64) {
     rows = rows_for(4096);
     L.pipe = 2;
@@ -183,9 +193,10 @@ inline Launch pick_launch(int nx, int ny, bool fp32, bool two_ahead) {
     const int v = std::atoi(e);
     if (v == 0 || v == 1 || v == 2) L.pipe = v;
   }
-  // two densities load rows one ahead; without the eight-wave shape above
-  // the FP32 form gets 4-wave strips with 64-row chunks on 4096^2 (measured
-  // 11.9k MLUPS, against 10.7k on eight-wave strips)
+  // two densities load rows one ahead and keep the shapes below the
+  // one-block-per-CU rule: the FP32 form gets 4-wave strips with 64-row
+  // chunks on 4096^2 (measured 11.9k MLUPS, against 10.7k on eight-wave
+  // strips, on the earlier plane-by-plane state)
   if (!two_ahead) L.pipe = 1;
   if (const char *e = std::getenv("LBE_CSF_ROWS")) {
     const int v = std::atoi(e);

@@ -23,6 +23,11 @@
 // the replay writes; the populations themselves are read only when the
 // relaxation times vary with c.
 //
+// The plane sets D (27 planes), M (3) and A (7, or 10 with the curvature
+// form) are row-interleaved like the state: plane p of site (x, y) in a set
+// of P planes sits at element (y P + p) nx + x (adj_index), so that a row of
+// tiles reads and writes one stretch of memory per row.
+//
 // The run is differentiated by sqrt(N) checkpointing: the forward run saves
 // every K-th state (K = ceil(sqrt N)); the backward pass replays each segment
 // from its checkpoint, writing the moment tape (and, with c-dependent
@@ -43,6 +48,12 @@ inline int adj_save_checkpoint(char *adj_base, const AdjLayout &A, int64_t k,
   if (k < 0 || k >= A.nchk) return 1;
   char *dst = adj_base + A.off_chk + (size_t)k * A.state_bytes;
   return hipMemcpyAsync(dst, state, bytes, hipMemcpyDeviceToDevice, st) == hipSuccess ? 0 : 1;
+}
+
+// element of plane p at (x, y) in a row-interleaved set of P planes
+__host__ __device__ __forceinline__ size_t adj_index(int P, int p, size_t nx, size_t y,
+                                                     size_t x) {
+  return (y * (size_t)P + (size_t)p) * nx + x;
 }
 
 struct AdjArgs {
@@ -296,14 +307,15 @@ adj_collide_kernel(const AdjArgs aa) {
   if (x < nx && y < ny) {
     const Consts<R> k(a);
     const uint32_t s = (uint32_t)(y * nx + x);
-    const uint32_t pb = (uint32_t)(n * sizeof(R));
+    constexpr uint32_t E = sizeof(R);
+    const uint32_t seg = (uint32_t)nx * E;   // one plane's segment of a row
     const __amdgpu_buffer_rsrc_t rd = plane_rsrc(aa.d_in, 27 * n * sizeof(R));
     const __amdgpu_buffer_rsrc_t rm = plane_rsrc(aa.m_in, 3 * n * sizeof(R));
-    auto ldD = [&](int q, uint32_t site) {
-      return buf_load<R>(rd, site * (uint32_t)sizeof(R), (uint32_t)q * pb);
+    auto ldD = [&](int q, int yy, int xx) {
+      return buf_load<R>(rd, (uint32_t)yy * 27u * seg + (uint32_t)xx * E, (uint32_t)q * seg);
     };
-    auto ldM = [&](int g, uint32_t site) {
-      return buf_load<R>(rm, site * (uint32_t)sizeof(R), (uint32_t)g * pb);
+    auto ldM = [&](int g, int yy, int xx) {
+      return buf_load<R>(rm, (uint32_t)yy * 3u * seg + (uint32_t)xx * E, (uint32_t)g * seg);
     };
     // lambda* = Stream^T lambda_{n+1}
     R lam[27];
@@ -312,16 +324,17 @@ adj_collide_kernel(const AdjArgs aa) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const bool out = (kEy[i] < 0 && bot) || (kEy[i] > 0 && top);
-      uint32_t src = s;
+      int sy = y, sx = x;
       int dq = i;
       if (out) {
         dq = kOpp[i];
       } else if (i != 0) {
-        src = (uint32_t)(wrapy(y + kEy[i]) * nx + wrapx(x + kEx[i]));
+        sy = wrapy(y + kEy[i]);
+        sx = wrapx(x + kEx[i]);
       }
-      lam[i] = ldD(dq, src) + ldM(0, src);
-      lam[9 + i] = ldD(9 + dq, src) + ldM(1, src);
-      const R lh = ldD(18 + dq, src) + ldM(2, src);
+      lam[i] = ldD(dq, sy, sx) + ldM(0, sy, sx);
+      lam[9 + i] = ldD(9 + dq, sy, sx) + ldM(1, sy, sx);
+      const R lh = ldD(18 + dq, sy, sx) + ldM(2, sy, sx);
       if (out) {
         lam[18 + i] = -lh;
         tw_acc += 2.0 * double(wq<R>(i)) * a.rcv * double(lh);
@@ -387,9 +400,12 @@ adj_collide_kernel(const AdjArgs aa) {
     const __amdgpu_buffer_rsrc_t wd = plane_rsrc(aa.d_out, 27 * n * sizeof(R));
     const __amdgpu_buffer_rsrc_t wa = plane_rsrc(aa.a, kAdjA * n * sizeof(R));
 #pragma unroll
-    for (int q = 0; q < 27; ++q) buf_store<R>(db[q], wd, s * (uint32_t)sizeof(R), (uint32_t)q * pb);
+    for (int q = 0; q < 27; ++q)
+      buf_store<R>(db[q], wd, (uint32_t)y * 27u * seg + (uint32_t)x * E, (uint32_t)q * seg);
 #pragma unroll
-    for (int m = 0; m < NA; ++m) buf_store<R>(da[m], wa, s * (uint32_t)sizeof(R), (uint32_t)m * pb);
+    for (int m = 0; m < NA; ++m)
+      buf_store<R>(da[m], wa, (uint32_t)y * (uint32_t)NA * seg + (uint32_t)x * E,
+                   (uint32_t)m * seg);
   }
   // dJ/dsigmaT: deterministic block sum, accumulated over the steps
   {
@@ -434,7 +450,8 @@ adj_stencil_kernel(const AdjArgs aa) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % aa.ntx) * kAdjTX, y0 = (tile / aa.ntx) * kAdjTY;
   const int tid = threadIdx.x;
-  const uint32_t pb = (uint32_t)(n * sizeof(R));
+  constexpr uint32_t E = sizeof(R);
+  const uint32_t seg = (uint32_t)nx * E;   // one plane's segment of a row
   const __amdgpu_buffer_rsrc_t ra = plane_rsrc(aa.a, kAdjA * n * sizeof(R));
   auto wrapx = [&](int v) {
     v %= nx;
@@ -452,9 +469,9 @@ adj_stencil_kernel(const AdjArgs aa) {
 #pragma unroll
       for (int m = 0; m < NA; ++m) la[m][r][q] = R(0);   // no stencil at a ghost site
     } else {
-      const uint32_t s = (uint32_t)(wrapy(row) * nx + wrapx(x0 - 1 + q));
+      const uint32_t off = (uint32_t)wrapy(row) * (uint32_t)NA * seg + (uint32_t)wrapx(x0 - 1 + q) * E;
 #pragma unroll
-      for (int m = 0; m < NA; ++m) la[m][r][q] = buf_load<R>(ra, s * (uint32_t)sizeof(R), (uint32_t)m * pb);
+      for (int m = 0; m < NA; ++m) la[m][r][q] = buf_load<R>(ra, off, (uint32_t)m * seg);
     }
   }
   __syncthreads();
@@ -496,23 +513,24 @@ adj_stencil_kernel(const AdjArgs aa) {
     }
     aa.dtw[(y == 0 ? 0 : nx) + x] += twb;
   }
-  const uint32_t s = (uint32_t)(y * nx + x);
+  const uint32_t off = (uint32_t)y * 3u * seg + (uint32_t)x * E;
   const __amdgpu_buffer_rsrc_t wm = plane_rsrc(aa.m_out, 3 * n * sizeof(R));
-  buf_store<R>(pbv, wm, s * (uint32_t)sizeof(R), 0u);
-  buf_store<R>(cb, wm, s * (uint32_t)sizeof(R), pb);
-  buf_store<R>(Tb * R(1.0 / a.rcv), wm, s * (uint32_t)sizeof(R), 2 * pb);
+  buf_store<R>(pbv, wm, off, 0u);
+  buf_store<R>(cb, wm, off, seg);
+  buf_store<R>(Tb * R(1.0 / a.rcv), wm, off, 2 * seg);
 }
 
 // lambda_N from the seed on c = sum_q g_q: D = the seed on each g_q, M = 0.
 template <typename R>
 __global__ void __launch_bounds__(256)
 adj_seed_kernel(R *__restrict__ d, R *__restrict__ m, const double *__restrict__ dJdc,
-                size_t n) {
+                size_t n, size_t nx) {
   const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (s >= n) return;
-  d[q * n + s] = (q >= 9 && q < 18) ? R(dJdc[s]) : R(0);
-  if (q < 3) m[q * n + s] = R(0);
+  const size_t y = s / nx, x = s - y * nx;
+  d[adj_index(27, q, nx, y, x)] = (q >= 9 && q < 18) ? R(dJdc[s]) : R(0);
+  if (q < 3) m[adj_index(3, q, nx, y, x)] = R(0);
 }
 
 // lambda_0 = D_0 + M_0 -> FP64 outputs: dJ/dF_0 (optional) and dJ/dT_0 through
@@ -520,13 +538,14 @@ adj_seed_kernel(R *__restrict__ d, R *__restrict__ m, const double *__restrict__
 template <typename R>
 __global__ void __launch_bounds__(256)
 adj_finish_kernel(const R *__restrict__ d, const R *__restrict__ m, double *__restrict__ dF0,
-                  double *__restrict__ dT0, size_t n, double rcv) {
+                  double *__restrict__ dT0, size_t n, size_t nx, double rcv) {
   const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
+  const size_t y = s / nx, x = s - y * nx;
   double t = 0.0;
 #pragma unroll
   for (int q = 0; q < 27; ++q) {
-    const double v = double(d[q * n + s]) + double(m[(q / 9) * n + s]);
+    const double v = double(d[adj_index(27, q, nx, y, x)]) + double(m[adj_index(3, q / 9, nx, y, x)]);
     if (dF0) dF0[q * n + s] = v;
     if (q >= 18) t += wq<double>(q - 18) * rcv * v;
   }

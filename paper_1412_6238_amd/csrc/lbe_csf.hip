@@ -308,10 +308,12 @@ int run_backward(lbe_csf *h, const double *dJdc, double *dsT, double *dTw, doubl
   const dim3 g27((unsigned)((n + 255) / 256), 27);
   if (f64)
     adj_seed_kernel<double><<<g27, 256, 0, st>>>(static_cast<double *>(D[0]),
-                                                 static_cast<double *>(M[0]), dJdc, n);
+                                                 static_cast<double *>(M[0]), dJdc, n,
+                                                 (size_t)nx);
   else
     adj_seed_kernel<float><<<g27, 256, 0, st>>>(static_cast<float *>(D[0]),
-                                                static_cast<float *>(M[0]), dJdc, n);
+                                                static_cast<float *>(M[0]), dJdc, n,
+                                                (size_t)nx);
   HIPCHK(h, hipGetLastError());
   int cur = 0;
   const int64_t N = h->rec_steps, K = h->rec_K;
@@ -367,11 +369,11 @@ int run_backward(lbe_csf *h, const double *dJdc, double *dsT, double *dTw, doubl
     if (f64)
       adj_finish_kernel<double><<<g1, 256, 0, st>>>(static_cast<const double *>(D[cur]),
                                                     static_cast<const double *>(M[cur]), dF0,
-                                                    dT0, n, h->base.rcv);
+                                                    dT0, n, (size_t)nx, h->base.rcv);
     else
       adj_finish_kernel<float><<<g1, 256, 0, st>>>(static_cast<const float *>(D[cur]),
                                                    static_cast<const float *>(M[cur]), dF0,
-                                                   dT0, n, h->base.rcv);
+                                                   dT0, n, (size_t)nx, h->base.rcv);
   }
   adj_sum_kernel<<<1, 256, 0, st>>>(part, nb, outv);
   HIPCHK(h, hipGetLastError());

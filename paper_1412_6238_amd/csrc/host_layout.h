@@ -163,19 +163,21 @@ inline Launch pick_launch(int nx, int ny, bool fp32, bool two_ahead) {
   };
   int rows = rows_for(2048);
   L.pipe = 1;
-  // One block per CU marching long chunks (one density): eight-wave strips
-  // loading rows two ahead in the FP32 step, four-wave strips loading one row
-  // ahead in FP64.  Measured on the row-interleaved state against the shapes
-  // below (interleaved timing windows after a warm-up, nine grids from
-  // 1024 x 512 to 8192 x 1024): FP32 up to 11% faster and none slower (the
-  // same on 4096^2 and 8192 x 1024, which already had this shape), FP64 2-8%
-  // faster everywhere, and within 1.5% of the best shape of a wider sweep.
-  // Taken when the chunks are at least four rows long.
+  // One block per CU marching long chunks: eight-wave strips loading rows
+  // two ahead in the FP32 step, four-wave strips loading one row ahead in
+  // FP64.  Measured on the row-interleaved state against the shapes below
+  // (interleaved timing windows after a warm-up, nine grids from 1024 x 512
+  // to 8192 x 1024): FP32 up to 11% faster and none slower (the same on
+  // 4096^2 and 8192 x 1024, which already had this shape), FP64 2-8% faster
+  // everywhere, and within 1.5% of the best shape of a wider sweep.  With two
+  // densities FP64 gains 0.3-6% on four grids; the FP32 form (rows one ahead)
+  // keeps the shapes below, which were as fast or within 4%.  Taken when the
+  // chunks are at least four rows long.
   const int nw1 = fp32 ? 8 : 4;
   const int nstr1 = (nx + 64 * nw1 - 1) / (64 * nw1);
   const int chunks1 = std::max(1, kNumCUs / nstr1);
   const int rows1 = (ny + chunks1 - 1) / chunks1;
-  const bool one_per_cu = two_ahead && nx >= 64 * nw1 && rows1 >= 4;
+  const bool one_per_cu = (two_ahead || !fp32) && nx >= 64 * nw1 && rows1 >= 4;
   if (one_per_cu && !std::getenv("LBE_CSF_NW")) {
     L.nw = nw1;
     L.nstrips = nstr1;

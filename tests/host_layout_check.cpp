@@ -77,15 +77,16 @@ static void check_layout(const lbe_csf_params &p, int64_t rec) {
   CHECK(sb - 1 <= 0xffffffffull, "state offsets fit 32 bits");
   const Launch la = pick_launch(p.nx, p.ny, !f64, !two_densities(&p));
   check_launch(la, p.nx, p.ny, two_densities(&p));
-  // one density, wide enough for a full strip and tall enough for chunks of
-  // four rows at one block per CU: that shape
+  // one density or FP64, wide enough for a full strip and tall enough for
+  // chunks of four rows at one block per CU: that shape
   {
     const int nw1 = f64 ? 4 : 8;
     const int nstr = (p.nx + 64 * nw1 - 1) / (64 * nw1);
     const int chunks = std::max(1, kNumCUs / nstr);
     const bool env = std::getenv("LBE_CSF_NW") || std::getenv("LBE_CSF_ROWS") ||
                      std::getenv("LBE_CSF_PIPE");
-    if (!env && !two_densities(&p) && p.nx >= 64 * nw1 && (p.ny + chunks - 1) / chunks >= 4)
+    if (!env && (!two_densities(&p) || f64) && p.nx >= 64 * nw1 &&
+        (p.ny + chunks - 1) / chunks >= 4)
       CHECK(la.nw == nw1 && la.nblocks <= kNumCUs && la.pipe == (f64 ? 1 : 2),
             "one block per CU (nw %d, %d blocks, pipe %d)", la.nw, la.nblocks, la.pipe);
   }

@@ -245,6 +245,41 @@ def test_small_grid_path_matches_per_step(lbe, monkeypatch, name, nx, ny, walls,
     assert out[0][1] == out[1][1] and out[0][2] == out[1][2] == 57
 
 
+@pytest.mark.parametrize("nx,ny,walls,extra", [(600, 389, 1, {}), (520, 400, 0, {"csf_form": 1})])
+def test_one_block_per_cu_ragged(lbe, oracle_mod, monkeypatch, nx, ny, walls, extra):
+    """The default launch on grids where one block per CU marches chunks of
+    a few rows, with a part-filled last strip and a short last chunk
+    (600 x 389: FP64 strips of 256 columns, 88 in the last, 5-row chunks,
+    4 in the last; FP32 strips of 512 columns, 4-row chunks, 1 in the last).
+    FP64 against the oracle at 1e-12, both forms bitwise equal to another
+    launch shape, and the FP32 form within 1e-5 of FP64."""
+    case = wl.random_case(nx, ny, seed=nx + 11 * ny, walls_y=walls, n_drops=6, **extra)
+    for k in ("LBE_CSF_NW", "LBE_CSF_ROWS", "LBE_CSF_PIPE"):
+        monkeypatch.delenv(k, raising=False)
+    _say(f"case one block per CU {nx}x{ny} walls={walls} {extra} fp64")
+    sim, orc = _pair(lbe, oracle_mod, case)
+    for n in (1, 3):
+        sim.step(n)
+        orc.step(n)
+        _cmp({"F": sim.get_state().cpu().numpy()}, {"F": orc.state()}, what=f"F after +{n}")
+    f64 = _fields_np(sim)
+    _say(f"case one block per CU {nx}x{ny} fp32_dev")
+    s32 = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                         case["Twall_top"], precision="fp32_dev")
+    s32.step(4)
+    _cmp(_fields_np(s32), f64, tol=1e-5, what="fp32 fields")
+    F32 = s32.get_state().cpu().numpy()
+    F64 = sim.get_state().cpu().numpy()
+    monkeypatch.setenv("LBE_CSF_NW", "2")
+    monkeypatch.setenv("LBE_CSF_ROWS", "7")
+    for precision, F in (("fp64", F64), ("fp32_dev", F32)):
+        _say(f"case one block per CU {nx}x{ny} {precision} against 2-wave 7-row chunks")
+        alt = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                             case["Twall_top"], precision=precision)
+        alt.step(4)
+        np.testing.assert_array_equal(alt.get_state().cpu().numpy(), F)
+
+
 def test_fp64_chunking_does_not_matter(lbe, oracle_mod, monkeypatch):
     """Different strip widths and chunk heights give bitwise-identical states."""
     case = wl.random_case(200, 60, seed=12, walls_y=1)

@@ -71,7 +71,7 @@ struct StepArgs {
   void *tape;
 };
 
-// Buffer resources: one descriptor per plane (scalar registers) and a 32-bit
+// Buffer resources: one descriptor per buffer (scalar registers) and a 32-bit
 // byte offset per lane, so a load or store needs one vector register for its
 // address instead of two.  The third descriptor word 0x00020000 is the CDNA
 // (gfx9 family) raw-buffer format; accesses past num_records return zero /
@@ -82,7 +82,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, s
 }
 
 // byte_off: per-lane offset (vector register); base: uniform offset (scalar
-// register), e.g. the start of a plane inside one descriptor for the state
+// register), e.g. a plane's segment within a row of the state
 template <typename T>
 __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off,
                                       uint32_t base = 0) {

@@ -3,8 +3,9 @@
 //
 // The library owns no device memory: every buffer is carved out of the
 // caller's workspace.  Layout (each region 256-byte aligned):
-//   state A, state B     25 planes (FP64, or FP32 deviations) + g_0 (FP64) and
-//                        hbar_0 (FP64, or an FP32 deviation)
+//   state A, state B     row-interleaved: per row, 25 plane segments (FP64, or
+//                        FP32 deviations), g_0 (FP64) and hbar_0 (FP64, or an
+//                        FP32 deviation)
 //   wall temperatures    2 * nx FP64 (bottom, top)
 //   partials             max blocks * 7 FP64 (per-block diagnostic sums)
 //   diag ring            4096 records of (step, 7 sums)

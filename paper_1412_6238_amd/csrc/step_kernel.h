@@ -13,17 +13,18 @@
 //   streaming    push to x + xi (x periodic); halfway bounce-back for f, g
 //                and anti-bounce-back with the wall temperature for hbar
 //
-// State layout (structure of arrays, x fastest): 25 planes of the storage
-// type S -- f_0..8, g_1..8, hbar_1..8 -- then the rest populations g_0 and
-// hbar_0.  The rest populations carry the two transported scalars (c = g_0 +
+// State layout (row-interleaved, x fastest; host_layout.h): each row holds
+// the row's segment of each of 25 planes of the storage type S -- f_0..8,
+// g_1..8, hbar_1..8 -- then those of the rest populations g_0 and hbar_0.
+// The rest populations carry the two transported scalars (c = g_0 +
 // small terms, rho cv T = hbar_0 + eight smaller terms).  g_0 stays FP64 in
 // both forms, which keeps c accurate to far below FP32 rounding (c enters
 // the force through eps^2 lap c); the FP32 form holds hbar_0 as an FP32
 // deviation.  The FP32 form therefore moves 2 x (26 x 4 + 8) = 224 bytes per
 // site update, against the 216 of 27 FP32 values.
 //
-// The state held is F_n (pre-collision).  A lane reads the planes of its own
-// site (coalesced, aligned) and pushes post-collision values to the
+// The state held is F_n (pre-collision).  A lane reads the 27 values of its
+// own site (coalesced, aligned) and pushes post-collision values to the
 // neighbours' slots in the other buffer (shifted by at most one element).
 //
 // Work decomposition: a block owns a strip of 64*NW columns and marches up a
@@ -295,8 +296,8 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     if (a.T) a.T[s] = DEV ? double(Tv) + Trow : double(Tv);
   }
   if (MODE & kStore) {
-    // one descriptor for the whole destination state (below 4 GiB); planes
-    // are selected by a scalar offset
+    // one descriptor for the whole destination state (below 4 GiB); a
+    // plane's segment within a row is selected by a scalar offset
     const __amdgpu_buffer_rsrc_t rd = plane_rsrc(a.dst, state_bytes_for<S>(n));
     const uint32_t pbytes = (uint32_t)(nx * sizeof(S));   // a plane's segment of a row
     const uint32_t RB = (uint32_t)row_bytes<S>(nx);
@@ -529,8 +530,8 @@ step_kernel(const StepArgs a) {
   const int hx = hside == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + nact == nx ? 0 : x0 + nact);
   const int hpos = hside == 0 ? 0 : nact + 1;
 
-  // one descriptor for the whole source state (below 4 GiB); planes are
-  // selected by a scalar offset
+  // one descriptor for the whole source state (below 4 GiB); a plane's
+  // segment within a row is selected by a scalar offset
   const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(src, state_bytes_for<S>(n));
   const uint32_t pbytes = (uint32_t)(nx * sizeof(S));   // a plane's segment of a row
   const uint32_t RB = (uint32_t)row_bytes<S>(nx);

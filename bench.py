@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -36,10 +37,20 @@ KERNEL_SOURCES = ("paper_1412_6238_amd/csrc/step_kernel.h", "paper_1412_6238_amd
                   "paper_1412_6238_amd/csrc/host_layout.h")
 
 
+def _code_only(text):
+    """C++ source without its comments and with runs of white space made one
+    space: what the compiler sees of it, up to formatting."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_hash():
+    """Hash of the code of the step kernel's sources (comments and
+    formatting excluded, so that editing them keeps the counter figures)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        h.update(_code_only(open(os.path.join(ROOT, f)).read()).encode())
     return h.hexdigest()[:16]
 
 

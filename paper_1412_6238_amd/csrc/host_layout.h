@@ -55,6 +55,17 @@ constexpr size_t rest_base(int which, size_t nx) {
   return kNumS * nx * sizeof(S) + (which ? nx * rest_bytes<S>(0) : 0);
 }
 
+// small-grid kernel: LDS bytes of the moments c (FP64), T and p (R) of the
+// grid with a halo column on each side and a row beyond each y boundary,
+// rounded up to 16 bytes (the resident states follow)
+template <typename R>
+constexpr size_t small_moment_bytes(size_t nx, size_t ny) {
+  return ((nx + 2) * (ny + 2) * (8 + 2 * sizeof(R)) + 15) / 16 * 16;
+}
+// ... which takes grids of up to this many sites, one per lane of a block
+// of at most as many lanes
+constexpr int kSmallMaxSites = 512;
+
 constexpr int kNumPartials = 7;  // mass, energy, cy, cx, mass_thr, cuy_thr, nonfinite
 
 // one diagnostic record: the step and the seven FP64 sums
@@ -301,19 +312,35 @@ inline Launch launch_for(const lbe_csf_params *p, size_t state_bytes) {
 // with a halo column on each side and a row beyond each y boundary, when
 // plain steps run many per launch of one block (small_step_kernel); 0 when
 // the grid is not small enough or has two densities.  LBE_CSF_SMALL=0 turns
-// the path off.  The limit is one site per lane of a 1024-lane block:
-// measured on MI355X, 8 x 64 runs 6.0 -> 5.0 us per step (FP32) and 7.2 ->
-// 6.5 (FP64) this way, while 40 x 100 (four sites per lane) runs 5.7 -> 26
-// us: one block's CU then serialises the arithmetic that one launch per
-// step spreads over a hundred blocks.
-constexpr size_t kSmallMaxSites = 1024;
+// the path off.  The limit is one site per lane of a 512-lane block.
+// Measured on MI355X with the row-interleaved state (one launch per step ->
+// this path): 16 x 32 FP32 5.80 -> 4.99 us per step with the moments in LDS,
+// 4.47 with the states too; 8 x 64 FP64 7.55 -> 6.65.  On 20 x 30 (600
+// sites, 640 lanes) the moments-only kernel was slower than one launch per
+// step (6.13 against 5.78 us), and on 40 x 100 (four sites per lane, plane
+// layout) one block took 26 us against 5.7: its CU serialises the arithmetic
+// that one launch per step spreads over a hundred blocks.
 inline size_t small_lds_bytes(const lbe_csf_params *p) {
   if (const char *e = std::getenv("LBE_CSF_SMALL"))
     if (std::atoi(e) == 0) return 0;
   const size_t n = (size_t)p->nx * p->ny;
-  if (two_densities(p) || n > kSmallMaxSites) return 0;
-  const size_t r = p->precision == LBE_CSF_FP64 ? 8 : 4;
-  return (size_t)(p->nx + 2) * (p->ny + 2) * (8 + 2 * r);
+  if (two_densities(p) || n > (size_t)kSmallMaxSites) return 0;
+  return p->precision == LBE_CSF_FP64 ? small_moment_bytes<double>(p->nx, p->ny)
+                                      : small_moment_bytes<float>(p->nx, p->ny);
+}
+// LDS of the variant that also keeps both states in LDS (small_step_kernel
+// with RES): the moments, then the two states; 0 where the small-grid path is
+// off or LBE_CSF_SMALL=1 asks for the moments-only variant.  Whether it fits
+// is the caller's test against the device's limit (160 KB on MI355X: every
+// FP32 small grid, FP64 grids up to about 340 sites).
+inline size_t small_res_bytes(const lbe_csf_params *p) {
+  const size_t m = small_lds_bytes(p);
+  if (m == 0) return 0;
+  if (const char *e = std::getenv("LBE_CSF_SMALL"))
+    if (std::atoi(e) == 1) return 0;
+  const size_t n = (size_t)p->nx * p->ny;
+  return m + 2 * (p->precision == LBE_CSF_FP64 ? state_bytes_for<double>(n)
+                                                 : state_bytes_for<float>(n));
 }
 
 }  // namespace host

@@ -61,6 +61,7 @@ struct lbe_csf {
   StepArgs base;      // constants filled once
   int device;         // the HIP device current at creation
   size_t small_lds;   // > 0: plain steps run many per launch (small grids)
+  bool small_res;     // ... with both states resident in LDS
 };
 
 namespace {
@@ -232,30 +233,40 @@ int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
 // Plain steps of a small grid, up to kSmallRun per launch of one block
 // (small_step_kernel); the states alternate as with one launch per step.
 constexpr int64_t kSmallRun = 4096;
-template <typename S, typename R, bool DEV, int MODE>
+template <typename S, typename R, bool DEV, int MODE, bool RES>
 hipError_t small_attr(size_t lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&small_step_kernel<S, R, DEV, MODE>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipFuncSetAttribute(
+      reinterpret_cast<const void *>(&small_step_kernel<S, R, DEV, MODE, RES>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+template <typename S, typename R, bool DEV, bool RES>
+hipError_t small_attrs(size_t lds) {
+  hipError_t e = small_attr<S, R, DEV, kStore, RES>(lds);
+  if (e == hipSuccess) e = small_attr<S, R, DEV, kStore | kCurv, RES>(lds);
+  return e;
 }
 template <typename S, typename R, bool DEV, int MODE>
-void small_launch(const StepArgs &a, void *other, int steps, int threads, size_t lds,
+void small_launch(const StepArgs &a, void *other, int steps, int threads, size_t lds, bool res,
                   hipStream_t st) {
-  small_step_kernel<S, R, DEV, MODE><<<1, threads, lds, st>>>(a, other, steps);
+  if (res) small_step_kernel<S, R, DEV, MODE, true><<<1, threads, lds, st>>>(a, other, steps);
+  else small_step_kernel<S, R, DEV, MODE, false><<<1, threads, lds, st>>>(a, other, steps);
 }
 
 int launch_small(lbe_csf *h, int64_t nsteps) {
   const size_t n = (size_t)h->P.nx * h->P.ny;
-  const int threads = (int)std::min<size_t>(1024, (n + 63) / 64 * 64);
+  const int threads = (int)std::min<size_t>(kSmallMaxSites, (n + 63) / 64 * 64);
   const bool f64 = h->P.precision == LBE_CSF_FP64, curv = h->P.csf_form == 1;
   while (nsteps > 0) {
     const int m = (int)std::min(nsteps, kSmallRun);
     StepArgs a = h->base;
     a.src = h->state[h->cur];
     void *other = h->state[1 - h->cur];
-    if (f64 && !curv) small_launch<double, double, false, kStore>(a, other, m, threads, h->small_lds, h->stream);
-    else if (f64) small_launch<double, double, false, kStore | kCurv>(a, other, m, threads, h->small_lds, h->stream);
-    else if (!curv) small_launch<float, float, true, kStore>(a, other, m, threads, h->small_lds, h->stream);
-    else small_launch<float, float, true, kStore | kCurv>(a, other, m, threads, h->small_lds, h->stream);
+    const size_t lds = h->small_lds;
+    const bool res = h->small_res;
+    if (f64 && !curv) small_launch<double, double, false, kStore>(a, other, m, threads, lds, res, h->stream);
+    else if (f64) small_launch<double, double, false, kStore | kCurv>(a, other, m, threads, lds, res, h->stream);
+    else if (!curv) small_launch<float, float, true, kStore>(a, other, m, threads, lds, res, h->stream);
+    else small_launch<float, float, true, kStore | kCurv>(a, other, m, threads, lds, res, h->stream);
     HIPCHK(h, hipGetLastError());
     if (m & 1) h->cur = 1 - h->cur;
     h->step += m;
@@ -470,6 +481,7 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   h->L = L;
   h->la = launch_for(params, L.state_bytes);
   h->small_lds = 0;
+  h->small_res = false;
   h->stream = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
   {
@@ -479,14 +491,21 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) !=
         hipSuccess)
       max_lds = 0;
-    const size_t lds = small_lds_bytes(params);
-    if (lds > 0 && lds <= (size_t)max_lds) {
-      const bool f64 = params->precision == LBE_CSF_FP64;
-      hipError_t e = f64 ? small_attr<double, double, false, kStore>(lds)
-                         : small_attr<float, float, true, kStore>(lds);
-      if (e == hipSuccess)
-        e = f64 ? small_attr<double, double, false, kStore | kCurv>(lds)
-                : small_attr<float, float, true, kStore | kCurv>(lds);
+    // both states in LDS where they fit, else the moments only
+    const bool f64 = params->precision == LBE_CSF_FP64;
+    const size_t lds_res = small_res_bytes(params), lds = small_lds_bytes(params);
+    if (lds_res > 0 && lds_res <= (size_t)max_lds) {
+      const hipError_t e = f64 ? small_attrs<double, double, false, true>(lds_res)
+                               : small_attrs<float, float, true, true>(lds_res);
+      if (e == hipSuccess) {
+        h->small_lds = lds_res;
+        h->small_res = true;
+      }
+      (void)hipGetLastError();
+    }
+    if (h->small_lds == 0 && lds > 0 && lds <= (size_t)max_lds) {
+      const hipError_t e = f64 ? small_attrs<double, double, false, false>(lds)
+                               : small_attrs<float, float, true, false>(lds);
       if (e == hipSuccess) h->small_lds = lds;
       (void)hipGetLastError();
     }

@@ -145,6 +145,19 @@ struct RowVals {
   __device__ __forceinline__ double h0() const { return rest_decode<rest_fmt<R>(1)>(h0r); }
 };
 
+// Plane-major layout of a state held in LDS by the small-grid kernel: g_0
+// (FP64), then hbar_0, then the 25 storage planes, each n values with the
+// site index y nx + x; every plane stays aligned to its element size, and
+// the lanes of a wave, holding consecutive sites, touch consecutive banks.
+template <typename S>
+__host__ __device__ constexpr size_t lds_rest_off(int which, size_t n) {
+  return which == 0 ? 0 : n * 8;
+}
+template <typename S>
+__host__ __device__ constexpr size_t lds_plane_off(int p, size_t n) {
+  return n * (8 + rest_bytes<S>(1)) + (size_t)p * n * sizeof(S);
+}
+
 // Moments of a loaded site: c (FP64), T or Delta T (FP64), p or Delta p
 // (sum f).  With two densities T = sum hbar / (rho(c) cv); in the FP32 form
 // the stored hbar deviates from w rho cv Trow (rho of the c = 0 fluid), so
@@ -175,12 +188,14 @@ __device__ __forceinline__ void site_moments(const RowVals<R> &r, double inv_rcv
 // The collision, diagnostics and field output of site (x, j).  cS/cC/cN,
 // tS.., pS.. point at the ring entries west of the site in rows j-1, j, j+1
 // (index 0 west, 1 centre, 2 east).
-template <typename S, typename R, bool DEV, int MODE>
+// With LDSOUT the post-collision values go to a state in LDS (lds_dst) in
+// the plane-major layout of lds_plane_off instead of to a.dst.
+template <typename S, typename R, bool DEV, int MODE, bool LDSOUT = false>
 __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &k, int j, int x,
                                             const double *cS, const double *cC, const double *cN,
                                             const R *tS, const R *tC, const R *tN, const R *pS,
                                             const R *pC, const R *pN, const RowVals<R> &cur,
-                                            double *acc) {
+                                            double *acc, char *lds_dst = nullptr) {
   constexpr bool VR = (MODE & kVarRho) != 0;
   const int nx = a.nx, ny = a.ny;
   const size_t n = (size_t)nx * (size_t)ny;
@@ -327,15 +342,23 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
     const bool walls = a.walls_y != 0;
     const bool bot = walls && j == 0, top = walls && j == ny - 1;
     const uint32_t own = (uint32_t)j * RB;   // this row's offset
-    auto st = [&](int q, uint32_t row_off, int xs, R val) {
-      buf_store<S>(S(val), rd, row_off + (uint32_t)xs * (uint32_t)sizeof(S),
-                   (uint32_t)plane_of(q) * pbytes);
+    // value of plane q to site (xs, row) (row_off = row * RB)
+    auto st = [&](int q, int row, uint32_t row_off, int xs, R val) {
+      if constexpr (LDSOUT)
+        *reinterpret_cast<S *>(lds_dst + lds_plane_off<S>(plane_of(q), n) +
+                               ((size_t)row * nx + xs) * sizeof(S)) = S(val);
+      else
+        buf_store<S>(S(val), rd, row_off + (uint32_t)xs * (uint32_t)sizeof(S),
+                     (uint32_t)plane_of(q) * pbytes);
     };
     // stores whose lines this wave writes whole
     constexpr bool stream = (MODE & kStream) != 0;
-    auto st_whole = [&](int q, uint32_t row_off, int xs, R val) {
+    auto st_whole = [&](int q, int row, uint32_t row_off, int xs, R val) {
       const uint32_t off = row_off + (uint32_t)xs * (uint32_t)sizeof(S);
-      if constexpr (stream)
+      if constexpr (LDSOUT)
+        *reinterpret_cast<S *>(lds_dst + lds_plane_off<S>(plane_of(q), n) +
+                               ((size_t)row * nx + xs) * sizeof(S)) = S(val);
+      else if constexpr (stream)
         buf_store_stream<S>(S(val), rd, off, (uint32_t)plane_of(q) * pbytes);
       else
         buf_store<S>(S(val), rd, off, (uint32_t)plane_of(q) * pbytes);
@@ -379,7 +402,7 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const R heq_full = rcvT * gam;
       const R hsrc = chf * src_h * fhe * heq_full;
       if (i == 0) {
-        st_whole(0, own, x, fo);
+        st_whole(0, j, own, x, fo);
         gsrc0 = gsrc;
         hsrc0 = hsrc;
         G0 = G;
@@ -402,12 +425,12 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
         const int o = kOpp[i];
         const double *tw = kEy[i] < 0 ? a.twb : a.twt;
         const R twv = DEV ? R(tw[x] - Trow) : R(tw[x]);
-        st(o, own, x, fo);
-        st(9 + o, own, x, go);
+        st(o, j, own, x, fo);
+        st(9 + o, j, own, x, go);
         if constexpr (DEV && VR)
-          st(18 + o, own, x, R(2) * w * (R(rcv_s) * twv + R(hoff_d)) - ho);
+          st(18 + o, j, own, x, R(2) * w * (R(rcv_s) * twv + R(hoff_d)) - ho);
         else
-          st(18 + o, own, x, R(2) * w * (VR ? R(rcv_s) : k.rcv) * twv - ho);
+          st(18 + o, j, own, x, R(2) * w * (VR ? R(rcv_s) : k.rcv) * twv - ho);
         dh += cur.v[18 + i] - ho;
       } else {
         int xd = x + kEx[i];
@@ -416,19 +439,19 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
         yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
         const uint32_t ro = (uint32_t)yd * RB;
         if (kEx[i] == 0) {
-          st_whole(i, ro, xd, fo);
-          st_whole(9 + i, ro, xd, go);
+          st_whole(i, yd, ro, xd, fo);
+          st_whole(9 + i, yd, ro, xd, go);
         } else {
-          st(i, ro, xd, fo);
-          st(9 + i, ro, xd, go);
+          st(i, yd, ro, xd, fo);
+          st(9 + i, yd, ro, xd, go);
         }
         // a move to the next row changes the reference by Tg xi_y
         const R shift = DEV && kEy[i] != 0 ? R(kEy[i]) * w * k.rcv * R(a.Tg) : R(0);
         const R hst = ho - shift;
         if (kEx[i] == 0)
-          st_whole(18 + i, ro, xd, hst);
+          st_whole(18 + i, yd, ro, xd, hst);
         else
-          st(18 + i, ro, xd, hst);
+          st(18 + i, yd, ro, xd, hst);
         dh += (cur.v[18 + i] - hst) - shift;
       }
     }
@@ -451,8 +474,16 @@ __device__ __forceinline__ void site_update(const StepArgs &a, const Consts<R> &
       const double hdiff = cur.h0() - rcv_s * Tfull_d * double(gam0);
       hnew = cur.h0() + double(-wT * R(hdiff) + hsrc0);
     }
-    rest_store<S, 0, stream>(gnew, rd, own, x, (uint32_t)rest_base<S>(0, nx));
-    rest_store<S, 1, stream>(hnew, rd, own, x, (uint32_t)rest_base<S>(1, nx));
+    if constexpr (LDSOUT) {
+      using T0 = typename RestRaw<rest_fmt<S>(0)>::T;
+      using T1 = typename RestRaw<rest_fmt<S>(1)>::T;
+      const size_t so = (size_t)j * nx + x;
+      *reinterpret_cast<T0 *>(lds_dst + lds_rest_off<S>(0, n) + so * sizeof(T0)) = T0(gnew);
+      *reinterpret_cast<T1 *>(lds_dst + lds_rest_off<S>(1, n) + so * sizeof(T1)) = T1(hnew);
+    } else {
+      rest_store<S, 0, stream>(gnew, rd, own, x, (uint32_t)rest_base<S>(0, nx));
+      rest_store<S, 1, stream>(hnew, rd, own, x, (uint32_t)rest_base<S>(1, nx));
+    }
   }
 }
 
@@ -758,8 +789,15 @@ step_kernel(const StepArgs a) {
 // need them through step_kernel).  All waves of a block share one CU and its
 // L1, so the block barrier also orders the global stores of one step before
 // the loads of the next.
-template <typename S, typename R, bool DEV, int MODE>
-__global__ void __launch_bounds__(1024)
+// With RES both states also live in LDS, after the moments (16-byte
+// aligned), plane-major (lds_plane_off): the source state is copied in at
+// the start, every step reads and writes LDS only, and the last state is
+// copied out to the global buffer that one launch per step would have left
+// it in.  Blocks of at most kSmallMaxSites (512) lanes leave each lane twice
+// the registers of a 1024-lane block, enough for the collision without
+// spilling.
+template <typename S, typename R, bool DEV, int MODE, bool RES>
+__global__ void __launch_bounds__(kSmallMaxSites)
 small_step_kernel(const StepArgs a0, void *other, int nsteps) {
   static_assert((MODE & (kDiag | kFields | kTape | kVarRho | kPress | kStream)) == 0,
                 "small grids: plain steps only");
@@ -781,17 +819,49 @@ small_step_kernel(const StepArgs a0, void *other, int nsteps) {
   StepArgs a = a0;
   const void *srcp = a0.src;
   void *dstp = other;
+  // resident states (RES): [2][state bytes] after the moments
+  const size_t sbytes = state_bytes_for<S>(n);
+  char *ls0 = reinterpret_cast<char *>(smem) + small_moment_bytes<R>(nx, ny);
+  char *lsrc = ls0, *ldst = ls0 + sbytes;
+  using T0 = typename RestRaw<rest_fmt<S>(0)>::T;
+  using T1 = typename RestRaw<rest_fmt<S>(1)>::T;
+  if constexpr (RES) {
+    // row-interleaved global state -> plane-major LDS
+    for (size_t i = threadIdx.x; i < n; i += nthr) {
+      const size_t y = i / nx, x = i - y * nx;
+      const char *g = static_cast<const char *>(a0.src) + y * RB;
+#pragma unroll
+      for (int p = 0; p < kNumS; ++p)
+        reinterpret_cast<S *>(lsrc + lds_plane_off<S>(p, n))[i] =
+            reinterpret_cast<const S *>(g + (size_t)p * pbytes)[x];
+      reinterpret_cast<T0 *>(lsrc + lds_rest_off<S>(0, n))[i] =
+          reinterpret_cast<const T0 *>(g + rb0)[x];
+      reinterpret_cast<T1 *>(lsrc + lds_rest_off<S>(1, n))[i] =
+          reinterpret_cast<const T1 *>(g + rb1)[x];
+    }
+    __syncthreads();
+  }
   for (int step = 0; step < nsteps; ++step) {
     const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(srcp, state_bytes_for<S>(n));
     auto load_site = [&](int y, int x, RowVals<R> &r) {
       const uint32_t ro = (uint32_t)y * RB;
+      if constexpr (RES) {
+        const size_t i = (size_t)y * nx + x;
 #pragma unroll
-      for (int q = 0; q < 27; ++q)
-        if (q != 9 && q != 18)
-          r.v[q] = R(buf_load<S>(rsrc, ro + (uint32_t)x * (uint32_t)sizeof(S),
-                                 (uint32_t)plane_of(q) * pbytes));
-      r.g0r = rest_load_raw<S, 0>(rsrc, ro, x, rb0);
-      r.h0r = rest_load_raw<S, 1>(rsrc, ro, x, rb1);
+        for (int q = 0; q < 27; ++q)
+          if (q != 9 && q != 18)
+            r.v[q] = R(reinterpret_cast<const S *>(lsrc + lds_plane_off<S>(plane_of(q), n))[i]);
+        r.g0r = reinterpret_cast<const T0 *>(lsrc + lds_rest_off<S>(0, n))[i];
+        r.h0r = reinterpret_cast<const T1 *>(lsrc + lds_rest_off<S>(1, n))[i];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 27; ++q)
+          if (q != 9 && q != 18)
+            r.v[q] = R(buf_load<S>(rsrc, ro + (uint32_t)x * (uint32_t)sizeof(S),
+                                   (uint32_t)plane_of(q) * pbytes));
+        r.g0r = rest_load_raw<S, 0>(rsrc, ro, x, rb0);
+        r.h0r = rest_load_raw<S, 1>(rsrc, ro, x, rb1);
+      }
     };
     // moments of every site, with the halo columns and the ghost rows
     for (int s = threadIdx.x; s < (int)n; s += nthr) {
@@ -841,13 +911,31 @@ small_step_kernel(const StepArgs a0, void *other, int nsteps) {
       RowVals<R> cur;
       load_site(y, x, cur);
       const size_t rS = (size_t)y * W + x, rC = rS + W, rN = rC + W;
-      site_update<S, R, DEV, MODE>(a, k, y, x, lc + rS, lc + rC, lc + rN, lt + rS, lt + rC,
-                                   lt + rN, lp + rS, lp + rC, lp + rN, cur, acc);
+      site_update<S, R, DEV, MODE, RES>(a, k, y, x, lc + rS, lc + rC, lc + rN, lt + rS,
+                                        lt + rC, lt + rN, lp + rS, lp + rC, lp + rN, cur, acc,
+                                        ldst);
     }
     __syncthreads();
     const void *t = srcp;
     srcp = dstp;
     dstp = const_cast<void *>(t);
+    char *lt2 = lsrc;
+    lsrc = ldst;
+    ldst = lt2;
+  }
+  if constexpr (RES) {
+    // the last state (plane-major LDS) to the buffer that holds it after an
+    // alternation of nsteps steps (row-interleaved)
+    for (size_t i = threadIdx.x; i < n; i += nthr) {
+      const size_t y = i / nx, x = i - y * nx;
+      char *g = static_cast<char *>(const_cast<void *>(srcp)) + y * RB;
+#pragma unroll
+      for (int p = 0; p < kNumS; ++p)
+        reinterpret_cast<S *>(g + (size_t)p * pbytes)[x] =
+            reinterpret_cast<const S *>(lsrc + lds_plane_off<S>(p, n))[i];
+      reinterpret_cast<T0 *>(g + rb0)[x] = reinterpret_cast<const T0 *>(lsrc + lds_rest_off<S>(0, n))[i];
+      reinterpret_cast<T1 *>(g + rb1)[x] = reinterpret_cast<const T1 *>(lsrc + lds_rest_off<S>(1, n))[i];
+    }
   }
 }
 

@@ -96,10 +96,16 @@ static void check_layout(const lbe_csf_params &p, int64_t rec) {
   CHECK(lf.nblocks == la.nblocks && lf.pipe == la.pipe, "launch_for shape");
   CHECK(lf.stream == (!f64 && !two_densities(&p) && 2 * sb > kLastLevelCache), "store policy");
   // the small-grid path: only one density, at most one site per lane of a
-  // 1024-lane block, and the LDS of the padded moment grid
-  const size_t sl = small_lds_bytes(&p);
-  if (two_densities(&p) || n > kSmallMaxSites) CHECK(sl == 0, "small path on %dx%d", p.nx, p.ny);
-  else CHECK(sl == (size_t)(p.nx + 2) * (p.ny + 2) * (f64 ? 24 : 16), "small LDS bytes");
+  // 512-lane block, and the LDS of the padded moment grid (16-byte rounded);
+  // with the states resident, both states after it
+  const size_t sl = small_lds_bytes(&p), sr = small_res_bytes(&p);
+  if (two_densities(&p) || n > (size_t)kSmallMaxSites) {
+    CHECK(sl == 0 && sr == 0, "small path on %dx%d", p.nx, p.ny);
+  } else {
+    const size_t m = (size_t)(p.nx + 2) * (p.ny + 2) * (f64 ? 24 : 16);
+    CHECK(sl >= m && sl < m + 16 && sl % 16 == 0, "small LDS bytes");
+    CHECK(sr == sl + 2 * sb, "resident small LDS bytes");
+  }
   const size_t offs[] = {L.off_a, L.off_b, L.off_tw, L.off_part, L.off_ring,
                          L.off_cnt, L.off_rec, L.off_pc, L.off_adj};
   for (size_t o : offs) CHECK(o % kAlign == 0, "offset %zu not aligned", o);

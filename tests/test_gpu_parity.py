@@ -219,21 +219,24 @@ def test_fp32_store_policy_does_not_matter(lbe, monkeypatch, extra):
 
 
 @pytest.mark.parametrize("name,nx,ny,walls,extra", [
-    ("poiseuille", 8, 64, 1, {}), ("random", 37, 21, 0, {"csf_form": 1}),
-    ("random", 30, 34, 1, {}), ("random", 3, 5, 0, {})])
+    ("poiseuille", 8, 64, 1, {}), ("random", 37, 13, 0, {"csf_form": 1}),
+    ("random", 16, 30, 1, {}), ("random", 17, 19, 1, {}), ("random", 3, 5, 0, {})])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
 def test_small_grid_path_matches_per_step(lbe, monkeypatch, name, nx, ny, walls, extra,
                                           precision):
-    """Small grids run their plain steps many per launch of one block
-    (small_step_kernel, the moments of the whole grid in LDS); the states are
-    bitwise those of one launch per step, with diagnostics every 7 steps
-    interleaved and an odd number of steps."""
+    """Small grids (up to 512 sites) run their plain steps many per launch
+    of one block (small_step_kernel, the moments of the whole grid in LDS, and
+    both states too where they fit: every one of these grids in FP32, 17 x 19
+    and 3 x 5 in FP64); the states are bitwise those of one launch per step,
+    with diagnostics every 7 steps interleaved and an odd number of steps.
+    LBE_CSF_SMALL: 0 one launch per step, 1 the moments-only kernel, 2 the
+    default (states resident where they fit)."""
     if name == "poiseuille":
         w = wl.make("poiseuille")
     else:
         w = wl.random_case(nx, ny, seed=nx + ny, walls_y=walls, **extra)
     out = []
-    for small in ("0", "1"):
+    for small in ("0", "1", "2"):
         monkeypatch.setenv("LBE_CSF_SMALL", small)
         _say(f"case small-grid path={small} {name} {nx}x{ny} {precision} {extra}")
         sim = lbe.Simulation(dict(w["params"], **extra), w["phi0"], w["T0"], w["Twall_bot"],
@@ -241,8 +244,9 @@ def test_small_grid_path_matches_per_step(lbe, monkeypatch, name, nx, ny, walls,
         sim.step(53)
         sim.step(4)
         out.append((sim.get_state().cpu().numpy(), sim.diag_history(), sim.step_count))
-    np.testing.assert_array_equal(out[0][0], out[1][0])
-    assert out[0][1] == out[1][1] and out[0][2] == out[1][2] == 57
+    for o in out[1:]:
+        np.testing.assert_array_equal(o[0], out[0][0])
+        assert o[1] == out[0][1] and o[2] == out[0][2] == 57
 
 
 @pytest.mark.parametrize("nx,ny,walls,extra", [(600, 389, 1, {}), (520, 400, 0, {"csf_form": 1})])

@@ -206,10 +206,10 @@ inline Launch pick_launch(int nx, int ny, bool fp32, bool two_ahead) {
     const int v = std::atoi(e);
     if (v == 0 || v == 1 || v == 2) L.pipe = v;
   }
-  // two densities load rows one ahead and keep the shapes below the
-  // one-block-per-CU rule: the FP32 form gets 4-wave strips with 64-row
-  // chunks on 4096^2 (measured 11.9k MLUPS, against 10.7k on eight-wave
-  // strips, on the earlier plane-by-plane state)
+  // two densities load rows one ahead; their FP32 form keeps the shapes
+  // after the one-block-per-CU rule: 4-wave strips with 64-row chunks on
+  // 4096^2 (measured 11.9k MLUPS, against 10.7k on eight-wave strips, on the
+  // earlier plane-by-plane state)
   if (!two_ahead) L.pipe = 1;
   if (const char *e = std::getenv("LBE_CSF_ROWS")) {
     const int v = std::atoi(e);

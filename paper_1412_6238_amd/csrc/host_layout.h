@@ -65,6 +65,12 @@ constexpr size_t small_moment_bytes(size_t nx, size_t ny) {
 // ... which takes grids of up to this many sites, one per lane of a block
 // of at most as many lanes
 constexpr int kSmallMaxSites = 512;
+// tile kernel (latency-bound grids): tiles of kTileX x kTileY sites, one per
+// lane of a block
+constexpr int kTileX = 64, kTileY = 4;
+inline int tile_blocks(int nx, int ny) {
+  return ((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY);
+}
 
 constexpr int kNumPartials = 7;  // mass, energy, cy, cx, mass_thr, cuy_thr, nonfinite
 
@@ -285,7 +291,9 @@ inline Layout make_layout(const lbe_csf_params *p, int64_t record_steps) {
   L.off_a = o; o = align_up(o + L.state_bytes);
   L.off_b = o; o = align_up(o + L.state_bytes);
   L.off_tw = o; o = align_up(o + 2 * (size_t)p->nx * 8);
-  L.off_part = o; o = align_up(o + (size_t)la.nblocks * kNumPartials * 8);
+  // diagnostic partials: one per block of the row-marching or the tile kernel
+  const size_t nparts = (size_t)std::max(la.nblocks, tile_blocks(p->nx, p->ny));
+  L.off_part = o; o = align_up(o + nparts * kNumPartials * 8);
   L.off_ring = o; o = align_up(o + (size_t)kDiagRing * sizeof(DiagRecord));
   L.off_cnt = o; o = align_up(o + 4 * sizeof(int64_t));
   L.off_rec = o; o = align_up(o + sizeof(DiagRecord));
@@ -332,6 +340,26 @@ inline size_t small_lds_bytes(const lbe_csf_params *p) {
   return p->precision == LBE_CSF_FP64 ? small_moment_bytes<double>(p->nx, p->ny)
                                       : small_moment_bytes<float>(p->nx, p->ny);
 }
+// Steps in tiles of one site per lane (tile_step_kernel) instead of
+// row-marching chunks, for one density on grids above the small-grid path
+// and up to 2^19 sites in FP64, 2^20 in FP32 (LBE_CSF_TILE=0/1 forces the
+// choice).  Measured on MI355X in interleaved windows against the
+// row-marching kernel: FP64 6-47% faster from 4,000 to 524,288 sites
+// (160 x 300: 7.1 against 12.6 us; 512 x 1024: 36.0 against 45.5), 2-19%
+// slower from 1024^2 up; FP32 4-29% faster up to 1024^2 (46.6 -> 39.3 us
+// there), level beyond.  One FP32 exception: grids whose last tile holds
+// fewer than 16 columns (200 x 100: 8.9 against 7.2 us, while 192 and 208
+// columns gain 10% and 20%) keep the row-marching kernel.
+inline bool use_tile_kernel(const lbe_csf_params *p) {
+  if (two_densities(p)) return false;
+  if (const char *e = std::getenv("LBE_CSF_TILE")) return std::atoi(e) == 1;
+  const size_t n = (size_t)p->nx * p->ny;
+  if (n <= (size_t)kSmallMaxSites) return false;
+  if (p->precision == LBE_CSF_FP64) return n <= (size_t)1 << 19;
+  const int tail = p->nx % kTileX;
+  return n <= (size_t)1 << 20 && !(tail > 0 && tail < 16);
+}
+
 // LDS of the variant that also keeps both states in LDS (small_step_kernel
 // with RES): the moments, then the two states; 0 where the small-grid path is
 // off or LBE_CSF_SMALL=1 asks for the moments-only variant.  Whether it fits

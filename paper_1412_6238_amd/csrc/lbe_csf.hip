@@ -60,6 +60,8 @@ struct lbe_csf {
   std::string err;
   StepArgs base;      // constants filled once
   int device;         // the HIP device current at creation
+  bool tile;          // steps in tiles (tile_step_kernel; latency-bound grids)
+  int diag_blocks;    // diagnostic partials per launch (blocks of the step kernel used)
   size_t small_lds;   // > 0: plain steps run many per launch (small grids)
   bool small_res;     // ... with both states resident in LDS
 };
@@ -200,6 +202,29 @@ bool launch_any(bool f64, int mode, const Launch &la, const StepArgs &a, hipStre
              : launch_prec<float, float, true>(mode, la, a, st);
 }
 
+// The tile kernel instantiated for this mode; false for a mode without one.
+template <typename S, typename R, bool DEV>
+bool launch_tile(int mode, int nb, const StepArgs &a, hipStream_t st) {
+  constexpr int T = kTileX * kTileY;
+  switch (mode) {
+    case kStore: tile_step_kernel<S, R, DEV, kStore><<<nb, T, 0, st>>>(a); return true;
+    case kStore | kDiag: tile_step_kernel<S, R, DEV, kStore | kDiag><<<nb, T, 0, st>>>(a); return true;
+    case kFields: tile_step_kernel<S, R, DEV, kFields><<<nb, T, 0, st>>>(a); return true;
+    case kDiag: tile_step_kernel<S, R, DEV, kDiag><<<nb, T, 0, st>>>(a); return true;
+    case kStore | kTape: tile_step_kernel<S, R, DEV, kStore | kTape><<<nb, T, 0, st>>>(a); return true;
+    case kTape: tile_step_kernel<S, R, DEV, kTape><<<nb, T, 0, st>>>(a); return true;
+    case kStore | kCurv: tile_step_kernel<S, R, DEV, kStore | kCurv><<<nb, T, 0, st>>>(a); return true;
+    case kStore | kDiag | kCurv:
+      tile_step_kernel<S, R, DEV, kStore | kDiag | kCurv><<<nb, T, 0, st>>>(a); return true;
+    case kFields | kCurv: tile_step_kernel<S, R, DEV, kFields | kCurv><<<nb, T, 0, st>>>(a); return true;
+    case kDiag | kCurv: tile_step_kernel<S, R, DEV, kDiag | kCurv><<<nb, T, 0, st>>>(a); return true;
+    case kStore | kTape | kCurv:
+      tile_step_kernel<S, R, DEV, kStore | kTape | kCurv><<<nb, T, 0, st>>>(a); return true;
+    case kTape | kCurv: tile_step_kernel<S, R, DEV, kTape | kCurv><<<nb, T, 0, st>>>(a); return true;
+    default: return false;
+  }
+}
+
 int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
                 double *ux, double *uy, double *p, double *T, void *tape = nullptr,
                 double *partials = nullptr) {
@@ -223,6 +248,17 @@ int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
       return fail(h, LBE_CSF_EINVAL, "no step kernel for mode " + std::to_string(pm));
     HIPCHK(h, hipGetLastError());
     mode |= kVarRho;
+  }
+  if (h->tile && a.drho == 0.0) {
+    // latency-bound grid: the step in tiles (tile_step_kernel)
+    const int nb = tile_blocks(h->P.nx, h->P.ny);
+    const int tm = mode & ~kStream;
+    const bool ok = h->P.precision == LBE_CSF_FP64
+                        ? launch_tile<double, double, false>(tm, nb, a, h->stream)
+                        : launch_tile<float, float, true>(tm, nb, a, h->stream);
+    if (!ok) return fail(h, LBE_CSF_EINVAL, "no tile kernel for mode " + std::to_string(tm));
+    HIPCHK(h, hipGetLastError());
+    return LBE_CSF_OK;
   }
   if (!launch_any(h->P.precision == LBE_CSF_FP64, mode, h->la, a, h->stream))
     return fail(h, LBE_CSF_EINVAL, "no step kernel for mode " + std::to_string(mode));
@@ -277,10 +313,10 @@ int launch_small(lbe_csf *h, int64_t nsteps) {
 
 int launch_reduce(lbe_csf *h, int64_t step, bool append) {
   if (append)
-    diag_reduce_kernel<<<1, 256, 0, h->stream>>>(h->partials, h->la.nblocks, h->ring,
+    diag_reduce_kernel<<<1, 256, 0, h->stream>>>(h->partials, h->diag_blocks, h->ring,
                                                  kDiagRing, h->counters, step);
   else
-    diag_reduce_kernel<<<1, 256, 0, h->stream>>>(h->partials, h->la.nblocks, h->rec, 1,
+    diag_reduce_kernel<<<1, 256, 0, h->stream>>>(h->partials, h->diag_blocks, h->rec, 1,
                                                  nullptr, step);
   HIPCHK(h, hipGetLastError());
   return LBE_CSF_OK;
@@ -482,6 +518,8 @@ int lbe_csf_create(const lbe_csf_params *params, void *workspace, size_t bytes,
   h->la = launch_for(params, L.state_bytes);
   h->small_lds = 0;
   h->small_res = false;
+  h->tile = use_tile_kernel(params);
+  h->diag_blocks = h->tile ? tile_blocks(params->nx, params->ny) : h->la.nblocks;
   h->stream = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
   {
@@ -648,9 +686,9 @@ int lbe_csf_diagnostics(lbe_csf *h, lbe_csf_diag *out) {
 
 int lbe_csf_diagnostics_noalloc(lbe_csf *h, lbe_csf_diag *out) {
   if (!h || !out) return h ? fail(h, LBE_CSF_EINVAL, "out is NULL") : LBE_CSF_EINVAL;
-  if (h->la.nblocks > kScratchMaxBlocks)
+  if (h->diag_blocks > kScratchMaxBlocks)
     return fail(h, LBE_CSF_EINVAL,
-                "diagnostics_noalloc: the launch has " + std::to_string(h->la.nblocks) +
+                "diagnostics_noalloc: the launch has " + std::to_string(h->diag_blocks) +
                     " blocks, the static scratch holds the partials of at most " +
                     std::to_string(kScratchMaxBlocks));
   int prev = 0;
@@ -669,7 +707,7 @@ int lbe_csf_diagnostics_noalloc(lbe_csf *h, lbe_csf_diag *out) {
     rc = launch_step(h, kDiag, h->state[h->cur], nullptr, nullptr, nullptr, nullptr, nullptr,
                      nullptr, nullptr, partials);
     if (rc == LBE_CSF_OK) {
-      diag_reduce_kernel<<<1, 256, 0, h->stream>>>(partials, h->la.nblocks, rec, 1, nullptr,
+      diag_reduce_kernel<<<1, 256, 0, h->stream>>>(partials, h->diag_blocks, rec, 1, nullptr,
                                                    h->step);
       DiagRecord r;
       hipError_t e = hipGetLastError();

@@ -939,4 +939,136 @@ small_step_kernel(const StepArgs a0, void *other, int nsteps) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Latency-bound grids: one plain step per launch in tiles of kTileX x kTileY
+// sites, one site per lane.  The row-marching kernel gives such grids chunks
+// of a row or two, and a chunk then waits for its own row, the rows above
+// and below and their halo columns one after another.  Here every lane
+// issues the loads of its own site and of at most one cell of the tile's
+// one-site frame (or of the site that a frame cell beyond the grid copies)
+// at once, forms the moments into an LDS tile, and after one barrier
+// collides its site with site_update.  The tile's cells hold what the row
+// kernel's ring holds (site_moments; beyond a wall c and p mirrored and
+// 2 T_wall - T; periodic wrap otherwise), so the states are bitwise the same.
+// One density; every mode of step_kernel but the streaming-store policy
+// (diagnostics: one FP64 partial per block, as there).
+template <typename S, typename R, bool DEV, int MODE>
+__global__ void __launch_bounds__(kTileX * kTileY)
+tile_step_kernel(const StepArgs a) {
+  static_assert((MODE & (kVarRho | kPress | kStream)) == 0, "tile kernel: one density");
+  constexpr int W = kTileX + 2, H = kTileY + 2;   // tile with its frame
+  constexpr int kFrame = 2 * W + 2 * kTileY;      // cells of the frame
+  constexpr int kWaves = kTileX * kTileY / 64;
+  static_assert(kFrame <= kTileX * kTileY, "one frame cell per lane at most");
+  __shared__ double lc[H * W];
+  __shared__ R lt[H * W];
+  __shared__ R lp[H * W];
+  __shared__ double red[kWaves][kNumPartials];
+  const int nx = a.nx, ny = a.ny;
+  const bool walls = a.walls_y != 0;
+  const size_t n = (size_t)nx * (size_t)ny;
+  const Consts<R> k(a);
+  const double inv_rcv = 1.0 / a.rcv;
+  const int ntx = (nx + kTileX - 1) / kTileX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % ntx) * kTileX, y0 = (tile / ntx) * kTileY;
+  const int tid = threadIdx.x;
+  const int lx = tid % kTileX, ly = tid / kTileX;
+  const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(a.src, state_bytes_for<S>(n));
+  const uint32_t pbytes = (uint32_t)(nx * sizeof(S));   // a plane's segment of a row
+  const uint32_t RB = (uint32_t)row_bytes<S>(nx);
+  const uint32_t rb0 = (uint32_t)rest_base<S>(0, nx), rb1 = (uint32_t)rest_base<S>(1, nx);
+  auto load_site = [&](int y, int x, RowVals<R> &r) {
+    const uint32_t ro = (uint32_t)y * RB;
+#pragma unroll
+    for (int q = 0; q < 27; ++q)
+      if (q != 9 && q != 18)
+        r.v[q] = R(buf_load<S>(rsrc, ro + (uint32_t)x * (uint32_t)sizeof(S),
+                               (uint32_t)plane_of(q) * pbytes));
+    r.g0r = rest_load_raw<S, 0>(rsrc, ro, x, rb0);
+    r.h0r = rest_load_raw<S, 1>(rsrc, ro, x, rb1);
+  };
+  // a cell of the tile (cx, cy in 0..W-1, 0..H-1, frame included): the site
+  // whose moments it holds, and whether it is a ghost beyond a wall (then the
+  // moments of the wall row, transformed)
+  struct Cell {
+    int sx, sy, ghost;   // ghost: 0 none, -1 below the bottom wall, 1 above the top
+  };
+  auto cell_of = [&](int cx, int cy) {
+    Cell c;
+    int gx = x0 - 1 + cx, gy = y0 - 1 + cy;
+    gx %= nx;
+    c.sx = gx < 0 ? gx + nx : gx;
+    c.ghost = 0;
+    if (walls && gy < 0) {
+      c.sy = 0;
+      c.ghost = -1;
+    } else if (walls && gy >= ny) {
+      c.sy = ny - 1;
+      c.ghost = 1;
+    } else {
+      gy %= ny;
+      c.sy = gy < 0 ? gy + ny : gy;
+    }
+    return c;
+  };
+  auto put_cell = [&](int idx, const Cell &c, const RowVals<R> &r) {
+    double cv, T;
+    R p;
+    site_moments<R, false>(r, inv_rcv, &cv, &T, &p);
+    const R Tr = R(T);
+    lc[idx] = cv;
+    lp[idx] = p;
+    if (c.ghost == 0) {
+      lt[idx] = Tr;
+    } else {
+      // beyond a wall: T_ghost = 2 T_wall - T with the wall temperature of
+      // the cell's column (deviations against the reference at the wall)
+      const bool bot = c.ghost < 0;
+      const double *tw = bot ? a.twb : a.twt;
+      const double twref = DEV ? a.Ts + (bot ? 0.0 : a.Tg * double(ny)) : 0.0;
+      const R twv = DEV ? R(tw[c.sx] - twref) : R(tw[c.sx]);
+      lt[idx] = R(2) * twv - Tr;
+    }
+  };
+  // this lane's own cell, and its frame cell (lanes 0 .. kFrame-1): frame
+  // rows cy = 0 and H-1 (W cells each), then columns cx = 0 and W-1 of the
+  // tile's rows
+  const int ocx = lx + 1, ocy = ly + 1;
+  const Cell own = cell_of(ocx, ocy);
+  int fcx = 0, fcy = 0;
+  if (tid < W) {
+    fcx = tid;
+    fcy = 0;
+  } else if (tid < 2 * W) {
+    fcx = tid - W;
+    fcy = H - 1;
+  } else if (tid < 2 * W + kTileY) {
+    fcx = 0;
+    fcy = tid - 2 * W + 1;
+  } else {
+    fcx = W - 1;
+    fcy = tid - 2 * W - kTileY + 1;
+  }
+  const bool has_frame = tid < kFrame;
+  const Cell fr = cell_of(fcx, fcy);
+  RowVals<R> cur, fv;
+  load_site(own.sy, own.sx, cur);
+  if (has_frame) load_site(fr.sy, fr.sx, fv);
+  put_cell(ocy * W + ocx, own, cur);
+  if (has_frame) put_cell(fcy * W + fcx, fr, fv);
+  __syncthreads();
+  const int x = x0 + lx, y = y0 + ly;
+  double acc[kNumPartials];
+#pragma unroll
+  for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
+  if (x < nx && y < ny) {
+    const int rS = ly * W + lx, rC = rS + W, rN = rC + W;
+    site_update<S, R, DEV, MODE>(a, k, y, x, lc + rS, lc + rC, lc + rN, lt + rS, lt + rC,
+                                 lt + rN, lp + rS, lp + rC, lp + rN, cur, acc);
+  }
+  if (MODE & kDiag)
+    block_partials<kWaves>(acc, red, tid, a.partials + (size_t)blockIdx.x * kNumPartials);
+}
+
 }  // namespace lbe

@@ -115,6 +115,7 @@ def test_curvature_launch_shapes_agree(lbe, monkeypatch, precision):
     """Row pipelines 0/1/2 and strip widths of 1, 2, 4, 8 waves give the same
     state, bit for bit."""
     case = _curv(wl.random_case(300, 40, seed=31, walls_y=1))
+    monkeypatch.setenv("LBE_CSF_TILE", "0")   # the row-marching kernel
     out = []
     for pipe, nw, rows in (("1", "4", "40"), ("0", "1", "7"), ("2", "2", "9"), ("2", "8", "13")):
         monkeypatch.setenv("LBE_CSF_PIPE", pipe)

@@ -182,6 +182,7 @@ def test_row_pipelines_agree(lbe, oracle_mod, monkeypatch, pipe, precision):
     """The ways of feeding rows (loaded twice, one row ahead, two rows ahead)
     give the same state, bit for bit, and FP64 matches the oracle."""
     case = wl.random_case(136, 40, seed=21, walls_y=1)
+    monkeypatch.setenv("LBE_CSF_TILE", "0")   # the row-marching kernel
     monkeypatch.setenv("LBE_CSF_PIPE", pipe)
     monkeypatch.setenv("LBE_CSF_ROWS", "7")
     _say(f"case pipeline {pipe} {precision} 136x40")
@@ -206,6 +207,7 @@ def test_fp32_store_policy_does_not_matter(lbe, monkeypatch, extra):
     (chosen by state size; forced both ways here) give the same state, bit
     for bit.  (The two-density step has no bypass variant.)"""
     case = wl.random_case(136, 40, seed=31, walls_y=1)
+    monkeypatch.setenv("LBE_CSF_TILE", "0")   # the row-marching kernel
     p = dict(case["params"], **extra)
     out = []
     for policy in ("0", "1"):
@@ -260,6 +262,7 @@ def test_one_block_per_cu_ragged(lbe, oracle_mod, monkeypatch, nx, ny, walls, ex
     case = wl.random_case(nx, ny, seed=nx + 11 * ny, walls_y=walls, n_drops=6, **extra)
     for k in ("LBE_CSF_NW", "LBE_CSF_ROWS", "LBE_CSF_PIPE"):
         monkeypatch.delenv(k, raising=False)
+    monkeypatch.setenv("LBE_CSF_TILE", "0")   # the row-marching kernel
     _say(f"case one block per CU {nx}x{ny} walls={walls} {extra} fp64")
     sim, orc = _pair(lbe, oracle_mod, case)
     for n in (1, 3):
@@ -284,9 +287,43 @@ def test_one_block_per_cu_ragged(lbe, oracle_mod, monkeypatch, nx, ny, walls, ex
         np.testing.assert_array_equal(alt.get_state().cpu().numpy(), F)
 
 
+@pytest.mark.parametrize("nx,ny,walls,extra", [(40, 100, 1, {}), (37, 21, 0, {"csf_form": 1}),
+                                               (130, 7, 1, {}), (65, 70, 0, {}), (3, 600, 1, {}),
+                                               (200, 3, 1, {"csf_form": 1})])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
+def test_tile_kernel_matches_row_kernel(lbe, monkeypatch, nx, ny, walls, extra, precision):
+    """Steps in tiles of one site per lane (tile_step_kernel, with its frame
+    of wrapped or ghost cells), diagnostic steps included, against the
+    row-marching kernel; grids narrower and shorter than a tile, ragged in
+    both directions, walls and periodic.  FP64: the states bitwise the same.
+    FP32: the same arithmetic, but the compiler fuses the FP32 multiply-adds
+    of the collision differently in the two kernels, so the states agree to
+    FP32 rounding (relative L2 under 1e-6).  The diagnostics are FP64 sums of
+    per-block partials over different blocks: equal to rounding."""
+    case = wl.random_case(nx, ny, seed=3 * nx + ny, walls_y=walls, n_drops=2, **extra)
+    out = []
+    for tile in ("0", "1"):
+        monkeypatch.setenv("LBE_CSF_TILE", tile)
+        _say(f"case tile kernel={tile} {nx}x{ny} walls={walls} {extra} {precision}")
+        sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                             case["Twall_top"], precision=precision, diag_every=4)
+        sim.step(9)
+        out.append((sim.get_state().cpu().numpy(), sim.diag_history()))
+    if precision == "fp64":
+        np.testing.assert_array_equal(out[1][0], out[0][0])
+    else:
+        assert _rel(out[1][0], out[0][0]) < 1e-6
+    assert len(out[1][1]) == len(out[0][1]) >= 2
+    for a, b in zip(out[1][1], out[0][1]):
+        assert a["step"] == b["step"]
+        for k in ("mass", "energy", "n_nonfinite"):
+            assert a[k] == pytest.approx(b[k], rel=1e-12 if precision == "fp64" else 1e-6), k
+
+
 def test_fp64_chunking_does_not_matter(lbe, oracle_mod, monkeypatch):
     """Different strip widths and chunk heights give bitwise-identical states."""
     case = wl.random_case(200, 60, seed=12, walls_y=1)
+    monkeypatch.setenv("LBE_CSF_TILE", "0")   # the row-marching kernel
     out = []
     for nw, rows in (("1", "3"), ("2", "7"), ("4", "60"), ("1", "1"), ("8", "13")):
         monkeypatch.setenv("LBE_CSF_NW", nw)

@@ -61,6 +61,7 @@ def test_noalloc_rejects_launch_beyond_scratch(lbe, monkeypatch):
     """One-row chunks on a tall grid make 20,000 blocks, more partials than
     the static scratch holds: EINVAL with a message, nothing launched."""
     monkeypatch.setenv("LBE_CSF_ROWS", "1")
+    monkeypatch.setenv("LBE_CSF_TILE", "0")   # the row-marching kernel
     nx, ny = 64, 20000
     case = wl.random_case(nx, ny, seed=4, walls_y=1, n_drops=1)
     _say(f"case noalloc over the limit {nx}x{ny}")

@@ -95,6 +95,9 @@ struct AdjLayout {
   size_t plane_bytes;     // one plane of the arithmetic type
   size_t off_chk;         // nchk states
   size_t off_tape;        // K states, then K moment sets
+  size_t off_tape2;       // a second tape, 2 states and K moment sets: with
+                          // constant relaxation times the replay of the next
+                          // segment fills it while the adjoint steps read the first
   size_t off_lam;         // D x2 (27 planes), M x2 (3 planes), A (kAdjA planes)
   size_t off_part;        // per-block FP64 partial sums of dJ/dsigmaT
   size_t off_tw;          // FP64 [2][nx] dJ/dTwall accumulators
@@ -128,6 +131,7 @@ inline AdjLayout adj_layout(int nx, int ny, size_t state_bytes, size_t value_byt
   size_t o = 0;
   A.off_chk = o; o += (size_t)A.nchk * A.state_bytes;
   A.off_tape = o; o += (size_t)A.K * (A.state_bytes + A.mom_bytes);
+  A.off_tape2 = o; o += 2 * A.state_bytes + (size_t)A.K * A.mom_bytes;
   A.off_lam = o; o += (2 * 27 + 2 * 3 + kAdjA) * A.plane_bytes;
   A.off_part = o; o += al((size_t)adj_tiles_x(nx) * adj_tiles_y(ny) * sizeof(double));
   A.off_tw = o; o += al(2 * (size_t)nx * sizeof(double));

@@ -64,6 +64,15 @@ struct lbe_csf {
   int diag_blocks;    // diagnostic partials per launch (blocks of the step kernel used)
   size_t small_lds;   // > 0: plain steps run many per launch (small grids)
   bool small_res;     // ... with both states resident in LDS
+  hipStream_t aux = nullptr;   // second stream of the backward pass (made on first use)
+  ~lbe_csf() {
+    if (aux) {
+      int prev = 0;
+      if (hipGetDevice(&prev) == hipSuccess && prev != device) (void)hipSetDevice(device);
+      (void)hipStreamDestroy(aux);
+      if (prev != device) (void)hipSetDevice(prev);
+    }
+  }
 };
 
 namespace {
@@ -225,9 +234,9 @@ bool launch_tile(int mode, int nb, const StepArgs &a, hipStream_t st) {
   }
 }
 
-int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
-                double *ux, double *uy, double *p, double *T, void *tape = nullptr,
-                double *partials = nullptr) {
+int launch_step_on(lbe_csf *h, hipStream_t stream, int mode, const void *src, void *dst,
+                   double *phi, double *ux, double *uy, double *p, double *T,
+                   void *tape = nullptr, double *partials = nullptr) {
   StepArgs a = h->base;
   if (partials) a.partials = partials;
   a.src = src;
@@ -244,7 +253,7 @@ int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
     // two densities: the pressure of Eq. 9 of the source state first (it
     // needs u, hence the force, at every site of the stencil)
     const int pm = kVarRho | kPress | (mode & kCurv);
-    if (!launch_any(h->P.precision == LBE_CSF_FP64, pm, h->la, a, h->stream))
+    if (!launch_any(h->P.precision == LBE_CSF_FP64, pm, h->la, a, stream))
       return fail(h, LBE_CSF_EINVAL, "no step kernel for mode " + std::to_string(pm));
     HIPCHK(h, hipGetLastError());
     mode |= kVarRho;
@@ -254,16 +263,22 @@ int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi,
     const int nb = tile_blocks(h->P.nx, h->P.ny);
     const int tm = mode & ~kStream;
     const bool ok = h->P.precision == LBE_CSF_FP64
-                        ? launch_tile<double, double, false>(tm, nb, a, h->stream)
-                        : launch_tile<float, float, true>(tm, nb, a, h->stream);
+                        ? launch_tile<double, double, false>(tm, nb, a, stream)
+                        : launch_tile<float, float, true>(tm, nb, a, stream);
     if (!ok) return fail(h, LBE_CSF_EINVAL, "no tile kernel for mode " + std::to_string(tm));
     HIPCHK(h, hipGetLastError());
     return LBE_CSF_OK;
   }
-  if (!launch_any(h->P.precision == LBE_CSF_FP64, mode, h->la, a, h->stream))
+  if (!launch_any(h->P.precision == LBE_CSF_FP64, mode, h->la, a, stream))
     return fail(h, LBE_CSF_EINVAL, "no step kernel for mode " + std::to_string(mode));
   HIPCHK(h, hipGetLastError());
   return LBE_CSF_OK;
+}
+
+int launch_step(lbe_csf *h, int mode, const void *src, void *dst, double *phi, double *ux,
+                double *uy, double *p, double *T, void *tape = nullptr,
+                double *partials = nullptr) {
+  return launch_step_on(h, h->stream, mode, src, dst, phi, ux, uy, p, T, tape, partials);
 }
 
 // Plain steps of a small grid, up to kSmallRun per launch of one block
@@ -374,28 +389,91 @@ int run_backward(lbe_csf *h, const double *dJdc, double *dsT, double *dTw, doubl
   aa.part = part;
   aa.dtw = tw;
   aa.ntx = ntx;
-  char *chk0 = base + A.off_chk, *tape0 = base + A.off_tape;
-  char *mom0 = tape0 + (size_t)A.K * A.state_bytes;
-  for (int64_t k = nseg - 1; k >= 0; --k) {
-    const int64_t m = std::min(K, N - k * K);
-    char *ck = chk0 + (size_t)k * A.state_bytes;
-    // state j of the segment: the checkpoint, then the tape slots (all of
-    // them with c-dependent relaxation times, else two rotating ones)
-    auto state = [&](int64_t j) -> void * {
-      if (j == 0) return ck;
-      return tape0 + (size_t)(vartau ? j : (j & 1)) * A.state_bytes;
-    };
-    auto moments = [&](int64_t j) -> void * { return mom0 + (size_t)j * A.mom_bytes; };
+  char *chk0 = base + A.off_chk;
+  // Tapes.  With c-dependent relaxation times the first tape holds all K
+  // states of a segment and its K moment sets.  With constant ones a segment
+  // needs two rotating state slots and its moment sets, and two tapes
+  // alternate: the replay of segment k - 1 fills one on a second stream while
+  // the adjoint steps of segment k read the other (events order the reuse).
+  char *tape_base[2] = {base + A.off_tape, base + A.off_tape2};
+  const size_t tape_states[2] = {(size_t)A.K, 2};
+  const bool overlap = !vartau && nseg > 1;
+  hipEvent_t ev_start = nullptr, ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
+  // the events are released on every way out of this function
+  struct EventSet {
+    hipEvent_t *e[5];
+    ~EventSet() {
+      for (hipEvent_t *p : e)
+        if (*p) (void)hipEventDestroy(*p);
+    }
+  } event_set{{&ev_start, &ev_rep[0], &ev_rep[1], &ev_adj[0], &ev_adj[1]}};
+  if (overlap) {
+    bool ok = true;
+    if (!h->aux) {
+      // on the handle's device, at the default priority
+      int prev = 0;
+      ok = hipGetDevice(&prev) == hipSuccess;
+      if (ok && prev != h->device) ok = hipSetDevice(h->device) == hipSuccess;
+      ok = ok && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess;
+      if (prev != h->device) (void)hipSetDevice(prev);
+    }
+    for (hipEvent_t *e : {&ev_start, &ev_rep[0], &ev_rep[1], &ev_adj[0], &ev_adj[1]})
+      ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    // the replays on the second stream start after everything queued so far
+    ok = ok && hipEventRecord(ev_start, st) == hipSuccess;
+    if (!ok) return fail(h, LBE_CSF_EDEVICE, "backward: could not set up the second stream");
+  }
+  auto seg_len = [&](int64_t k) { return std::min(K, N - k * K); };
+  // state j of segment k on tape b: the checkpoint, then the tape slots
+  auto state = [&](int64_t k, int b, int64_t j) -> void * {
+    if (j == 0) return chk0 + (size_t)k * A.state_bytes;
+    return tape_base[b] + (size_t)(vartau ? j : (j & 1)) * A.state_bytes;
+  };
+  auto moments = [&](int b, int64_t j) -> void * {
+    return tape_base[b] + tape_states[b] * A.state_bytes + (size_t)j * A.mom_bytes;
+  };
+  // the forward steps of segment k from its checkpoint, writing the moment
+  // tape (and, with c-dependent relaxation times, keeping the states)
+  auto replay = [&](int64_t k, int b, hipStream_t on) {
+    const int64_t m = seg_len(k);
     for (int64_t j = 0; j < m; ++j) {
       const bool last = j + 1 == m;   // its successor is not needed
-      const int rc = launch_step(h, last ? kTape : (kStore | kTape), state(j),
-                                 last ? nullptr : state(j + 1), nullptr, nullptr, nullptr,
-                                 nullptr, nullptr, moments(j));
+      const int rc = launch_step_on(h, on, last ? kTape : (kStore | kTape), state(k, b, j),
+                                    last ? nullptr : state(k, b, j + 1), nullptr, nullptr,
+                                    nullptr, nullptr, nullptr, moments(b, j));
+      if (rc != LBE_CSF_OK) return rc;
+    }
+    return (int)LBE_CSF_OK;
+  };
+  auto tape_of = [&](int64_t k) { return overlap ? (int)(k & 1) : 0; };
+  if (overlap) {
+    const int rc = replay(nseg - 1, tape_of(nseg - 1), st);
+    if (rc != LBE_CSF_OK) return rc;
+  }
+  for (int64_t k = nseg - 1; k >= 0; --k) {
+    const int64_t m = seg_len(k);
+    const int b = tape_of(k);
+    if (overlap) {
+      if (k > 0) {
+        // segment k - 1 into the other tape, once the adjoint steps of
+        // segment k + 1 (which read that tape) are done
+        const int bn = tape_of(k - 1);
+        hipError_t e = hipStreamWaitEvent(h->aux, k + 1 < nseg ? ev_adj[bn] : ev_start, 0);
+        int rc = e == hipSuccess ? replay(k - 1, bn, h->aux) : (int)LBE_CSF_EDEVICE;
+        if (rc == LBE_CSF_OK && hipEventRecord(ev_rep[bn], h->aux) != hipSuccess)
+          rc = LBE_CSF_EDEVICE;
+        if (rc != LBE_CSF_OK)
+          return rc == LBE_CSF_EDEVICE ? fail(h, rc, "backward: second stream") : rc;
+      }
+      if (k < nseg - 1 && hipStreamWaitEvent(st, ev_rep[b], 0) != hipSuccess)
+        return fail(h, LBE_CSF_EDEVICE, "backward: stream wait");
+    } else {
+      const int rc = replay(k, b, st);
       if (rc != LBE_CSF_OK) return rc;
     }
     for (int64_t j = m - 1; j >= 0; --j) {
-      aa.s.src = vartau ? state(j) : nullptr;
-      aa.s.tape = moments(j);
+      aa.s.src = vartau ? state(k, b, j) : nullptr;
+      aa.s.tape = moments(b, j);
       aa.d_in = D[cur];
       aa.m_in = M[cur];
       aa.d_out = D[1 - cur];
@@ -408,8 +486,12 @@ int run_backward(lbe_csf *h, const double *dJdc, double *dsT, double *dTw, doubl
         if (curv) launch_adj<float, true, true>(vartau, aa, nb, st);
         else launch_adj<float, true, false>(vartau, aa, nb, st);
       }
-      HIPCHK(h, hipGetLastError());
+      if (hipGetLastError() != hipSuccess)
+        return fail(h, LBE_CSF_EDEVICE, "backward: adjoint kernel launch");
       cur = 1 - cur;
+    }
+    if (overlap && hipEventRecord(ev_adj[b], st) != hipSuccess) {
+      return fail(h, LBE_CSF_EDEVICE, "backward: event record");
     }
   }
   const unsigned g1 = (unsigned)((n + 255) / 256);
@@ -427,6 +509,7 @@ int run_backward(lbe_csf *h, const double *dJdc, double *dsT, double *dTw, doubl
   HIPCHK(h, hipGetLastError());
   if (dTw) HIPCHK(h, hipMemcpyAsync(dTw, tw, 2 * (size_t)nx * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(h, hipMemcpyAsync(dsT, outv, sizeof(double), hipMemcpyDeviceToHost, st));
+  // the stream has waited for every replay of the second stream
   HIPCHK(h, hipStreamSynchronize(st));
   return LBE_CSF_OK;
 }

@@ -124,7 +124,9 @@ static void check_layout(const lbe_csf_params &p, int64_t rec) {
     CHECK(A.nchk * A.K >= rec && (A.nchk - 1) * A.K < rec, "checkpoints");
     CHECK(A.state_bytes >= sb && A.state_bytes % 256 == 0, "checkpoint state size");
     CHECK(A.off_tape >= A.off_chk + (size_t)A.nchk * A.state_bytes, "checkpoint region");
-    CHECK(A.off_lam >= A.off_tape + (size_t)A.K * (A.state_bytes + A.mom_bytes), "tape");
+    CHECK(A.off_tape2 >= A.off_tape + (size_t)A.K * (A.state_bytes + A.mom_bytes), "tape");
+    CHECK(A.off_lam >= A.off_tape2 + 2 * A.state_bytes + (size_t)A.K * A.mom_bytes,
+          "second tape");
     CHECK(A.off_part >= A.off_lam + (2 * 27 + 2 * 3 + kAdjA) * A.plane_bytes, "cotangents");
     CHECK(A.off_tw >= A.off_part + (size_t)adj_tiles_x(p.nx) * adj_tiles_y(p.ny) * 8, "adj part");
     CHECK(A.total >= A.off_tw + 2 * (size_t)p.nx * 8 + 8, "adj total");

@@ -230,6 +230,22 @@ bool launch_tile(int mode, int nb, const StepArgs &a, hipStream_t st) {
     case kStore | kTape | kCurv:
       tile_step_kernel<S, R, DEV, kStore | kTape | kCurv><<<nb, T, 0, st>>>(a); return true;
     case kTape | kCurv: tile_step_kernel<S, R, DEV, kTape | kCurv><<<nb, T, 0, st>>>(a); return true;
+    default: break;
+  }
+  // two densities: the pressure pass, then the step
+  constexpr int V = kVarRho, P = kVarRho | kPress;
+  switch (mode) {
+    case P: tile_step_kernel<S, R, DEV, P><<<nb, T, 0, st>>>(a); return true;
+    case P | kCurv: tile_step_kernel<S, R, DEV, P | kCurv><<<nb, T, 0, st>>>(a); return true;
+    case V | kStore: tile_step_kernel<S, R, DEV, V | kStore><<<nb, T, 0, st>>>(a); return true;
+    case V | kStore | kDiag: tile_step_kernel<S, R, DEV, V | kStore | kDiag><<<nb, T, 0, st>>>(a); return true;
+    case V | kFields: tile_step_kernel<S, R, DEV, V | kFields><<<nb, T, 0, st>>>(a); return true;
+    case V | kDiag: tile_step_kernel<S, R, DEV, V | kDiag><<<nb, T, 0, st>>>(a); return true;
+    case V | kStore | kCurv: tile_step_kernel<S, R, DEV, V | kStore | kCurv><<<nb, T, 0, st>>>(a); return true;
+    case V | kStore | kDiag | kCurv:
+      tile_step_kernel<S, R, DEV, V | kStore | kDiag | kCurv><<<nb, T, 0, st>>>(a); return true;
+    case V | kFields | kCurv: tile_step_kernel<S, R, DEV, V | kFields | kCurv><<<nb, T, 0, st>>>(a); return true;
+    case V | kDiag | kCurv: tile_step_kernel<S, R, DEV, V | kDiag | kCurv><<<nb, T, 0, st>>>(a); return true;
     default: return false;
   }
 }
@@ -249,6 +265,26 @@ int launch_step_on(lbe_csf *h, hipStream_t stream, int mode, const void *src, vo
   a.T = T;
   if (h->P.csf_form == 1) mode |= kCurv;
   if (h->la.stream && (mode & kStore) && !(mode & kTape)) mode |= kStream;
+  if (h->tile) {
+    // latency-bound grid: the step in tiles (tile_step_kernel); with two
+    // densities the pressure pass first, as below
+    const int nb = tile_blocks(h->P.nx, h->P.ny);
+    const bool f64 = h->P.precision == LBE_CSF_FP64;
+    int tm = mode & ~kStream;
+    if (a.drho != 0.0) {
+      const int pm = kVarRho | kPress | (tm & kCurv);
+      if (!(f64 ? launch_tile<double, double, false>(pm, nb, a, stream)
+                : launch_tile<float, float, true>(pm, nb, a, stream)))
+        return fail(h, LBE_CSF_EINVAL, "no tile kernel for mode " + std::to_string(pm));
+      HIPCHK(h, hipGetLastError());
+      tm |= kVarRho;
+    }
+    if (!(f64 ? launch_tile<double, double, false>(tm, nb, a, stream)
+              : launch_tile<float, float, true>(tm, nb, a, stream)))
+      return fail(h, LBE_CSF_EINVAL, "no tile kernel for mode " + std::to_string(tm));
+    HIPCHK(h, hipGetLastError());
+    return LBE_CSF_OK;
+  }
   if (a.drho != 0.0) {
     // two densities: the pressure of Eq. 9 of the source state first (it
     // needs u, hence the force, at every site of the stencil)
@@ -257,17 +293,6 @@ int launch_step_on(lbe_csf *h, hipStream_t stream, int mode, const void *src, vo
       return fail(h, LBE_CSF_EINVAL, "no step kernel for mode " + std::to_string(pm));
     HIPCHK(h, hipGetLastError());
     mode |= kVarRho;
-  }
-  if (h->tile && a.drho == 0.0) {
-    // latency-bound grid: the step in tiles (tile_step_kernel)
-    const int nb = tile_blocks(h->P.nx, h->P.ny);
-    const int tm = mode & ~kStream;
-    const bool ok = h->P.precision == LBE_CSF_FP64
-                        ? launch_tile<double, double, false>(tm, nb, a, stream)
-                        : launch_tile<float, float, true>(tm, nb, a, stream);
-    if (!ok) return fail(h, LBE_CSF_EINVAL, "no tile kernel for mode " + std::to_string(tm));
-    HIPCHK(h, hipGetLastError());
-    return LBE_CSF_OK;
   }
   if (!launch_any(h->P.precision == LBE_CSF_FP64, mode, h->la, a, stream))
     return fail(h, LBE_CSF_EINVAL, "no step kernel for mode " + std::to_string(mode));

@@ -950,12 +950,15 @@ small_step_kernel(const StepArgs a0, void *other, int nsteps) {
 // collides its site with site_update.  The tile's cells hold what the row
 // kernel's ring holds (site_moments; beyond a wall c and p mirrored and
 // 2 T_wall - T; periodic wrap otherwise), so the states are bitwise the same.
-// One density; every mode of step_kernel but the streaming-store policy
-// (diagnostics: one FP64 partial per block, as there).
+// Every mode of step_kernel but the streaming-store policy (diagnostics: one
+// FP64 partial per block, as there); with two densities the pressure pass
+// and the step, whose cells take p from the pressure plane as the ring does.
 template <typename S, typename R, bool DEV, int MODE>
 __global__ void __launch_bounds__(kTileX * kTileY)
 tile_step_kernel(const StepArgs a) {
-  static_assert((MODE & (kVarRho | kPress | kStream)) == 0, "tile kernel: one density");
+  static_assert((MODE & kStream) == 0, "tile kernel: default store policy");
+  constexpr bool VR = (MODE & kVarRho) != 0;
+  constexpr bool VRP = VR && !(MODE & kPress);
   constexpr int W = kTileX + 2, H = kTileY + 2;   // tile with its frame
   constexpr int kFrame = 2 * W + 2 * kTileY;      // cells of the frame
   constexpr int kWaves = kTileX * kTileY / 64;
@@ -1015,10 +1018,12 @@ tile_step_kernel(const StepArgs a) {
   auto put_cell = [&](int idx, const Cell &c, const RowVals<R> &r) {
     double cv, T;
     R p;
-    site_moments<R, false>(r, inv_rcv, &cv, &T, &p);
+    // with two densities T needs the reference temperature of the site's row
+    const double tref = DEV ? a.Ts + a.Tg * (double(c.sy) + 0.5) : 0.0;
+    site_moments<R, VR>(r, inv_rcv, &cv, &T, &p, a.rho, a.drho, a.cv, tref);
     const R Tr = R(T);
     lc[idx] = cv;
-    lp[idx] = p;
+    lp[idx] = VRP ? R(a.pc[(size_t)c.sy * nx + c.sx]) : p;
     if (c.ghost == 0) {
       lt[idx] = Tr;
     } else {

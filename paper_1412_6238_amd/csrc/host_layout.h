@@ -347,14 +347,15 @@ inline size_t small_lds_bytes(const lbe_csf_params *p) {
 // Steps in tiles of one site per lane (tile_step_kernel) instead of
 // row-marching chunks, on grids above the small-grid path and up to 2^19
 // sites in FP64, 2^20 in FP32, with one density or two (LBE_CSF_TILE=0/1
-// forces the choice).  With two densities the tiles were 13-45% faster on
-// six grids from 64 x 64 to 1024^2 (160 x 300 FP64: 11.8 against 21.5 us).  Measured on MI355X in interleaved windows against the
-// row-marching kernel: FP64 6-47% faster from 4,000 to 524,288 sites
-// (160 x 300: 7.1 against 12.6 us; 512 x 1024: 36.0 against 45.5), 2-19%
-// slower from 1024^2 up; FP32 4-29% faster up to 1024^2 (46.6 -> 39.3 us
-// there), level beyond.  One FP32 exception: grids whose last tile holds
-// fewer than 16 columns (200 x 100: 8.9 against 7.2 us, while 192 and 208
-// columns gain 10% and 20%) keep the row-marching kernel.
+// forces the choice).  Measured on MI355X in interleaved windows against
+// the row-marching kernel, one density: FP64 6-47% faster from 4,000 to
+// 524,288 sites (160 x 300: 7.1 against 12.6 us; 512 x 1024: 36.0 against
+// 45.5), 2-19% slower from 1024^2 up; FP32 4-29% faster up to 1024^2
+// (46.6 -> 39.3 us there), 12-33% slower beyond (2048^2: 212 against 185
+// us).  Two densities: 13-45% faster on six grids from 64 x 64 to 1024^2
+// (160 x 300 FP64: 11.8 against 21.5 us).  One FP32 exception: grids whose
+// last tile holds fewer than 16 columns (200 x 100: 8.9 against 7.2 us,
+// while 192 and 208 columns gain 10% and 20%) keep the row-marching kernel.
 inline bool use_tile_kernel(const lbe_csf_params *p) {
   if (const char *e = std::getenv("LBE_CSF_TILE")) return std::atoi(e) == 1;
   const size_t n = (size_t)p->nx * p->ny;

@@ -353,16 +353,27 @@ inline size_t small_lds_bytes(const lbe_csf_params *p) {
 // 45.5), 2-19% slower from 1024^2 up; FP32 4-29% faster up to 1024^2
 // (46.6 -> 39.3 us there), 12-33% slower beyond (2048^2: 212 against 185
 // us).  Two densities: 13-45% faster on six grids from 64 x 64 to 1024^2
-// (160 x 300 FP64: 11.8 against 21.5 us).  One FP32 exception: grids whose
-// last tile holds fewer than 16 columns (200 x 100: 8.9 against 7.2 us,
-// while 192 and 208 columns gain 10% and 20%) keep the row-marching kernel.
+// (160 x 300 FP64: 11.8 against 21.5 us).  The exception: short grids two
+// or four tiles wide whose last tile holds 1 to 8 columns keep the
+// row-marching kernel, in FP32 below 65,536 sites (200 x 100: 8.8 against
+// 7.3 us; 65-72 and 193-200 columns, 64 to 400 rows, 15-27% slower in
+// tiles; 200 x 300 even; 70 x 1000 and 200 x 1000 4% and 11% faster), in
+// FP64 the two-tile grids below 20,000 sites (70 x 100 to 70 x 250: 7-9%
+// slower; 68 x 400 14% faster).  Every other short last tile runs faster in
+// tiles (73-79, 129-143, 201-206 and 257-1033 columns: FP32 11-42%, FP64
+// 19-49%).  The slowdown sits in the collision and stores: without them the
+// tile kernel takes the same ~4 us at every width; the order of the tiles
+// over the XCDs, the partial tile placed first and one block per CU leave it
+// unchanged.  Its cause was not found.
 inline bool use_tile_kernel(const lbe_csf_params *p) {
   if (const char *e = std::getenv("LBE_CSF_TILE")) return std::atoi(e) == 1;
   const size_t n = (size_t)p->nx * p->ny;
   if (n <= (size_t)kSmallMaxSites) return false;
-  if (p->precision == LBE_CSF_FP64) return n <= (size_t)1 << 19;
-  const int tail = p->nx % kTileX;
-  return n <= (size_t)1 << 20 && !(tail > 0 && tail < 16);
+  const bool fp64 = p->precision == LBE_CSF_FP64;
+  const int ntx = (p->nx + kTileX - 1) / kTileX, tail = p->nx % kTileX;
+  const bool short_tail = tail >= 1 && tail <= 8;
+  if (fp64) return n <= (size_t)1 << 19 && !(short_tail && ntx == 2 && n < 20000);
+  return n <= (size_t)1 << 20 && !(short_tail && (ntx == 2 || ntx == 4) && n < 65536);
 }
 
 // LDS of the variant that also keeps both states in LDS (small_step_kernel

@@ -203,6 +203,27 @@ int main() {
     CHECK(!params_valid(&p, &why) && !why.empty(), "%s accepted", b.what);
   }
   CHECK(!params_valid(nullptr, nullptr), "NULL params accepted");
+  // the step kernel chosen at measured points (tiles or row-marching chunks)
+  unsetenv("LBE_CSF_TILE");
+  struct TileCase {
+    int nx, ny, prec;
+    bool tile;
+  };
+  const TileCase tiles[] = {
+      {16, 32, LBE_CSF_FP32_DEV, false},    {40, 100, LBE_CSF_FP32_DEV, true},
+      {200, 100, LBE_CSF_FP32_DEV, false},  {200, 100, LBE_CSF_FP64, true},
+      {201, 100, LBE_CSF_FP32_DEV, true},   {200, 1000, LBE_CSF_FP32_DEV, true},
+      {70, 100, LBE_CSF_FP64, false},       {70, 100, LBE_CSF_FP32_DEV, false},
+      {68, 400, LBE_CSF_FP64, true},        {70, 1000, LBE_CSF_FP32_DEV, true},
+      {130, 100, LBE_CSF_FP32_DEV, true},   {520, 100, LBE_CSF_FP32_DEV, true},
+      {1024, 1024, LBE_CSF_FP32_DEV, true}, {1024, 1024, LBE_CSF_FP64, false},
+      {2048, 1024, LBE_CSF_FP32_DEV, false}};
+  for (const TileCase &t : tiles) {
+    lbe_csf_params p = base(t.nx, t.ny);
+    p.precision = t.prec;
+    CHECK(use_tile_kernel(&p) == t.tile, "%dx%d prec %d: tile kernel %d expected", t.nx, t.ny,
+          t.prec, (int)t.tile);
+  }
   if (g_fail) return 1;
   std::printf("ok %ld\n", cases);
   return 0;

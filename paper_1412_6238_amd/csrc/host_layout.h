@@ -345,14 +345,17 @@ inline size_t small_lds_bytes(const lbe_csf_params *p) {
                                       : small_moment_bytes<float>(p->nx, p->ny);
 }
 // Steps in tiles of one site per lane (tile_step_kernel) instead of
-// row-marching chunks, on grids above the small-grid path and up to 2^19
-// sites in FP64, 2^20 in FP32, with one density or two (LBE_CSF_TILE=0/1
-// forces the choice).  Measured on MI355X in interleaved windows against
-// the row-marching kernel, one density: FP64 6-47% faster from 4,000 to
-// 524,288 sites (160 x 300: 7.1 against 12.6 us; 512 x 1024: 36.0 against
-// 45.5), 2-19% slower from 1024^2 up; FP32 4-29% faster up to 1024^2
-// (46.6 -> 39.3 us there), 12-33% slower beyond (2048^2: 212 against 185
-// us).  Two densities: 13-45% faster on six grids from 64 x 64 to 1024^2
+// row-marching chunks, on grids above the small-grid path and up to 1.5M
+// sites, with one density or two (LBE_CSF_TILE=0/1 forces the choice).
+// Measured on MI355X in interleaved windows against the row-marching
+// kernel, one density: FP32 4-42% faster up to 1.44M sites (1024^2: 40.3
+// against 50.3 us; 1500 x 700: 41.2 against 52.1), 7-13% slower from 1.5M
+// up (2048 x 1024: 111 against 98 us; 4096^2: 918 against 690); FP64 6-49%
+// faster up to 2^19 sites (160 x 300: 7.1 against 12.6 us; 512 x 1024: 36.0
+// against 45.5) and 3-19% faster up to 1.44M where the width is not a
+// multiple of the row kernel's 256-column strips (800^2: 63.3 against 78.4;
+// 1030 x 1000: 101 against 114), 1-3% slower where it is (1024^2, 2048 x
+// 512).  Two densities: 13-45% faster on six grids from 64 x 64 to 1024^2
 // (160 x 300 FP64: 11.8 against 21.5 us).  The exception: short grids two
 // or four tiles wide whose last tile holds 1 to 8 columns keep the
 // row-marching kernel, in FP32 below 65,536 sites (200 x 100: 8.8 against
@@ -372,8 +375,11 @@ inline bool use_tile_kernel(const lbe_csf_params *p) {
   const bool fp64 = p->precision == LBE_CSF_FP64;
   const int ntx = (p->nx + kTileX - 1) / kTileX, tail = p->nx % kTileX;
   const bool short_tail = tail >= 1 && tail <= 8;
-  if (fp64) return n <= (size_t)1 << 19 && !(short_tail && ntx == 2 && n < 20000);
-  return n <= (size_t)1 << 20 && !(short_tail && (ntx == 2 || ntx == 4) && n < 65536);
+  if (fp64) {
+    if (short_tail && ntx == 2 && n < 20000) return false;
+    return n <= (size_t)1 << 19 || (n <= 1500000 && p->nx % 256 != 0);
+  }
+  return n <= 1500000 && !(short_tail && (ntx == 2 || ntx == 4) && n < 65536);
 }
 
 // LDS of the variant that also keeps both states in LDS (small_step_kernel

@@ -217,7 +217,10 @@ int main() {
       {68, 400, LBE_CSF_FP64, true},        {70, 1000, LBE_CSF_FP32_DEV, true},
       {130, 100, LBE_CSF_FP32_DEV, true},   {520, 100, LBE_CSF_FP32_DEV, true},
       {1024, 1024, LBE_CSF_FP32_DEV, true}, {1024, 1024, LBE_CSF_FP64, false},
-      {2048, 1024, LBE_CSF_FP32_DEV, false}};
+      {2048, 1024, LBE_CSF_FP32_DEV, false}, {1500, 700, LBE_CSF_FP32_DEV, true},
+      {1500, 1500, LBE_CSF_FP32_DEV, false}, {1030, 1000, LBE_CSF_FP64, true},
+      {800, 800, LBE_CSF_FP64, true},       {2048, 512, LBE_CSF_FP64, false},
+      {2048, 1024, LBE_CSF_FP64, false},    {4096, 4096, LBE_CSF_FP32_DEV, false}};
   for (const TileCase &t : tiles) {
     lbe_csf_params p = base(t.nx, t.ny);
     p.precision = t.prec;

@@ -289,13 +289,14 @@ def test_one_block_per_cu_ragged(lbe, oracle_mod, monkeypatch, nx, ny, walls, ex
 
 @pytest.mark.parametrize("nx,ny,walls,extra", [(40, 100, 1, {}), (37, 21, 0, {"csf_form": 1}),
                                                (130, 7, 1, {}), (65, 70, 0, {}), (3, 600, 1, {}),
-                                               (200, 3, 1, {"csf_form": 1})])
+                                               (200, 3, 1, {"csf_form": 1}), (1030, 1000, 1, {})])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
 def test_tile_kernel_matches_row_kernel(lbe, monkeypatch, nx, ny, walls, extra, precision):
     """Steps in tiles of one site per lane (tile_step_kernel, with its frame
     of wrapped or ghost cells), diagnostic steps included, against the
     row-marching kernel; grids narrower and shorter than a tile, ragged in
-    both directions, walls and periodic.  FP64: the states bitwise the same.
+    both directions, walls and periodic, and a ragged grid of a million sites
+    (4,000 tiles: the diagnostic partials at the size where the tiles end).  FP64: the states bitwise the same.
     FP32: the same arithmetic, but the compiler fuses the FP32 multiply-adds
     of the collision differently in the two kernels, so the states agree to
     FP32 rounding (relative L2 under 1e-6).  The diagnostics are FP64 sums of

@@ -356,30 +356,17 @@ inline size_t small_lds_bytes(const lbe_csf_params *p) {
 // multiple of the row kernel's 256-column strips (800^2: 63.3 against 78.4;
 // 1030 x 1000: 101 against 114), 1-3% slower where it is (1024^2, 2048 x
 // 512).  Two densities: 13-45% faster on six grids from 64 x 64 to 1024^2
-// (160 x 300 FP64: 11.8 against 21.5 us).  The exception: short grids two
-// or four tiles wide whose last tile holds 1 to 8 columns keep the
-// row-marching kernel, in FP32 below 65,536 sites (200 x 100: 8.8 against
-// 7.3 us; 65-72 and 193-200 columns, 64 to 400 rows, 15-27% slower in
-// tiles; 200 x 300 even; 70 x 1000 and 200 x 1000 4% and 11% faster), in
-// FP64 the two-tile grids below 20,000 sites (70 x 100 to 70 x 250: 7-9%
-// slower; 68 x 400 14% faster).  Every other short last tile runs faster in
-// tiles (73-79, 129-143, 201-206 and 257-1033 columns: FP32 11-42%, FP64
-// 19-49%).  The slowdown sits in the collision and stores: without them the
-// tile kernel takes the same ~4 us at every width; the order of the tiles
-// over the XCDs, the partial tile placed first and one block per CU leave it
-// unchanged.  Its cause was not found.
+// (160 x 300 FP64: 11.8 against 21.5 us).  On grids whose last tile holds
+// 1 to 8 columns this relies on the tile kernel's lanes beyond the last
+// column colliding their wrapped sites: left idle, they made 200 x 100
+// FP32 take 8.7 us in tiles against 7.2 on the row-marching kernel; now 5.8.
 inline bool use_tile_kernel(const lbe_csf_params *p) {
   if (const char *e = std::getenv("LBE_CSF_TILE")) return std::atoi(e) == 1;
   const size_t n = (size_t)p->nx * p->ny;
   if (n <= (size_t)kSmallMaxSites) return false;
-  const bool fp64 = p->precision == LBE_CSF_FP64;
-  const int ntx = (p->nx + kTileX - 1) / kTileX, tail = p->nx % kTileX;
-  const bool short_tail = tail >= 1 && tail <= 8;
-  if (fp64) {
-    if (short_tail && ntx == 2 && n < 20000) return false;
+  if (p->precision == LBE_CSF_FP64)
     return n <= (size_t)1 << 19 || (n <= 1500000 && p->nx % 256 != 0);
-  }
-  return n <= 1500000 && !(short_tail && (ntx == 2 || ntx == 4) && n < 65536);
+  return n <= 1500000;
 }
 
 // LDS of the variant that also keeps both states in LDS (small_step_kernel

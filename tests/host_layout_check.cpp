@@ -211,9 +211,9 @@ int main() {
   };
   const TileCase tiles[] = {
       {16, 32, LBE_CSF_FP32_DEV, false},    {40, 100, LBE_CSF_FP32_DEV, true},
-      {200, 100, LBE_CSF_FP32_DEV, false},  {200, 100, LBE_CSF_FP64, true},
+      {200, 100, LBE_CSF_FP32_DEV, true},  {200, 100, LBE_CSF_FP64, true},
       {201, 100, LBE_CSF_FP32_DEV, true},   {200, 1000, LBE_CSF_FP32_DEV, true},
-      {70, 100, LBE_CSF_FP64, false},       {70, 100, LBE_CSF_FP32_DEV, false},
+      {70, 100, LBE_CSF_FP64, true},       {70, 100, LBE_CSF_FP32_DEV, true},
       {68, 400, LBE_CSF_FP64, true},        {70, 1000, LBE_CSF_FP32_DEV, true},
       {130, 100, LBE_CSF_FP32_DEV, true},   {520, 100, LBE_CSF_FP32_DEV, true},
       {1024, 1024, LBE_CSF_FP32_DEV, true}, {1024, 1024, LBE_CSF_FP64, false},

@@ -313,18 +313,22 @@ def test_two_densities_fp32_multi_droplet(lbe):
     _fp32_vs_fp64(lbe, w, 2000, "multi_droplet")
 
 
+@pytest.mark.parametrize("nx", [150, 196])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
-def test_two_densities_tile_kernel_matches_row_kernel(lbe, monkeypatch, precision):
+def test_two_densities_tile_kernel_matches_row_kernel(lbe, monkeypatch, precision, nx):
     """Two densities in tiles (the pressure pass, then the step, each with its
     frame of wrapped or ghost cells) against the row-marching kernel on a
     grid ragged in both directions, diagnostics included: FP64 bitwise, FP32
-    to rounding (the compiler fuses the FP32 multiply-adds differently)."""
-    base = wl.random_case(150, 45, seed=46, walls_y=1)
+    to rounding (the compiler fuses the FP32 multiply-adds differently).
+    196 columns: four tiles, the last of 4 columns, whose other lanes collide
+    their wrapped sites (pressure pass included) and write what the owning
+    lanes write."""
+    base = wl.random_case(nx, 45, seed=46, walls_y=1)
     case = _two(base, 2.5 * base["params"]["rho"])
     out = []
     for tile in ("0", "1"):
         monkeypatch.setenv("LBE_CSF_TILE", tile)
-        _say(f"case two densities tile kernel={tile} 150x45 {precision}")
+        _say(f"case two densities tile kernel={tile} {nx}x45 {precision}")
         sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
                              case["Twall_top"], precision=precision, diag_every=3)
         sim.step(7)

@@ -321,6 +321,45 @@ def test_tile_kernel_matches_row_kernel(lbe, monkeypatch, nx, ny, walls, extra, 
             assert a[k] == pytest.approx(b[k], rel=1e-12 if precision == "fp64" else 1e-6), k
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
+def test_tile_kernel_short_last_tile_outputs(lbe, monkeypatch, precision):
+    """A grid two tiles wide whose last tile holds 6 columns: the tile
+    kernel's lanes beyond the last column collide their wrapped sites and
+    store what the owning lanes store.  Every output against the row-marching
+    kernel: the fields, the diagnostics, and the gradients of a recorded run
+    (its tape written by the tile kernel).  FP64 bitwise, FP32 to rounding."""
+    import torch
+    case = wl.random_case(70, 30, seed=77, walls_y=1, n_drops=2)
+    rng = np.random.default_rng(77)
+    seed_field = torch.as_tensor(rng.standard_normal((30, 70)))
+    out = []
+    for tile in ("0", "1"):
+        monkeypatch.setenv("LBE_CSF_TILE", tile)
+        _say(f"case short last tile kernel={tile} 70x30 {precision}")
+        sim = lbe.Simulation(case["params"], case["phi0"], case["T0"], case["Twall_bot"],
+                             case["Twall_top"], precision=precision, diag_every=2,
+                             record_steps=9)
+        sim.step(9, record=True)
+        g = sim.backward(seed_field, want_F0=True, want_T0=True)
+        f = sim.fields()
+        torch.cuda.synchronize()
+        out.append(dict(state=sim.get_state().cpu().numpy(),
+                        **{k: v.cpu().numpy() for k, v in f.items()},
+                        sigmaT=np.array([g["sigmaT"]]), Twall=g["Twall"].cpu().numpy(),
+                        F0=g["F0"].cpu().numpy(), T0=g["T0"].cpu().numpy(),
+                        mass=np.array([d["mass"] for d in sim.diag_history()])))
+    assert out[0]["mass"].size >= 4
+    for key in out[0]:
+        a, b = out[1][key], out[0][key]
+        if precision == "fp64" and key != "mass":
+            np.testing.assert_array_equal(a, b, err_msg=key)
+        else:
+            # FP32: states and fields to rounding, gradients through a tape
+            # that differs at that rounding
+            tol = 1e-5 if key in ("sigmaT", "Twall", "F0", "T0") else 1e-6
+            assert _rel(a, b) < tol, key
+
+
 def test_fp64_chunking_does_not_matter(lbe, oracle_mod, monkeypatch):
     """Different strip widths and chunk heights give bitwise-identical states."""
     case = wl.random_case(200, 60, seed=12, walls_y=1)

@@ -356,10 +356,11 @@ inline size_t small_lds_bytes(const lbe_csf_params *p) {
 // multiple of the row kernel's 256-column strips (800^2: 63.3 against 78.4;
 // 1030 x 1000: 101 against 114), 1-3% slower where it is (1024^2, 2048 x
 // 512).  Two densities: 13-45% faster on six grids from 64 x 64 to 1024^2
-// (160 x 300 FP64: 11.8 against 21.5 us).  On grids whose last tile holds
-// 1 to 8 columns this relies on the tile kernel's lanes beyond the last
-// column colliding their wrapped sites: left idle, they made 200 x 100
-// FP32 take 8.7 us in tiles against 7.2 on the row-marching kernel; now 5.8.
+// (160 x 300 FP64: 11.8 against 21.5 us).  On grids two or four tiles wide
+// whose last tile holds 1 to 8 columns this relies on the tile kernel's
+// lanes beyond the last column colliding their wrapped sites: left idle,
+// they made 200 x 100 FP32 take 8.7 us in tiles against 7.2 on the
+// row-marching kernel; now 5.8.
 inline bool use_tile_kernel(const lbe_csf_params *p) {
   if (const char *e = std::getenv("LBE_CSF_TILE")) return std::atoi(e) == 1;
   const size_t n = (size_t)p->nx * p->ny;
